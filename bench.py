@@ -1,0 +1,216 @@
+#!/usr/bin/env python
+"""Throughput of the GPU backward induction on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload day_5min]
+
+A step is one full backward induction of the workload: for every stage the expectation
+W_t = P_t V_{t+1} (MFMA) and the max-plus Bellman sweep with argmax, writing V_1 and all
+int16 policies to HBM.  The metric is feasible state-action updates per second (the
+(t, k, s, j) candidates of the solve over the wall time of a step), inputs resident in
+HBM before the timed region.  One JSON line is printed; besides the required fields it
+carries:
+  roofline      the Bellman-sweep kernel (dominant): feasible candidates per launch over
+                its average launch time measured with HIP events on the solve's stream
+                during the timed steps, against the VALU issue bound;
+  cpu_baseline  the FP64 oracle timed on this host's cores on a bounded sample;
+  extra         the year-long hourly solve, the adjoint/value time ratio and the
+                batched/looped comparison, each on the same GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+# Peak of the sweep: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 3.93e13 VALU lane-instructions/s;
+# one candidate needs at least one v_add_f32 and half a v_max3_f32 (1.5 instructions).
+VALU_LANE_OPS = 256 * 64 * 2.4e9
+SWEEP_PEAK_GUPD = VALU_LANE_OPS / 1.5 / 1e9
+
+
+def host_cores() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def timed_solves(dp, torch, inst, steps, warmup, events=True):
+    lam = torch.from_numpy(inst.lam).cuda()
+    P = torch.from_numpy(inst.P).cuda()
+    solver = dp.Solver(lam, P, inst.storage, store_all=False, policy=True)
+    for _ in range(warmup):
+        solver.run()
+    torch.cuda.synchronize()
+    if events:
+        dp.kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        solver.run()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    timing = None
+    if events:
+        timing = dp.kernel_timing()
+        dp.kernel_timing(False)
+    del solver
+    return (t1 - t0) / steps, timing
+
+
+def roofline_of(inst, timing):
+    sweep_ms, n_sweep, exp_ms, n_exp = timing
+    per_launch = inst.candidates() / inst.T            # candidates per sweep launch (avg)
+    avg_s = sweep_ms / 1e3 / max(n_sweep, 1)
+    achieved = per_launch / avg_s / 1e9
+    return {
+        "bound": "alu", "achieved": round(achieved, 1), "peak": round(SWEEP_PEAK_GUPD, 1),
+        "unit": "Gupd/s", "frac": round(achieved / SWEEP_PEAK_GUPD, 4), "traffic": None,
+        "kernel": "sweep_kernel", "avg_launch_us": round(avg_s * 1e6, 3),
+        "launches": n_sweep,
+        "expectation_avg_launch_us": round(exp_ms / 1e3 / max(n_exp, 1) * 1e6, 3),
+    }
+
+
+def cpu_baseline(inst, budget_s=12.0):
+    import oracle
+    cores = host_cores()
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        oracle.solve(inst.storage, inst.lam, inst.P, keep_all=False, want_policy=True,
+                     threads=cores)
+        n += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": round(inst.candidates() * n / dt, 1), "unit": "updates/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{n} full solve(s) of {inst.name} (FP64 C loops, OpenMP over k)"}
+
+
+def adjoint_ratio(dp, torch, inst, reps=5):
+    lam = torch.from_numpy(inst.lam).cuda()
+    P = torch.from_numpy(inst.P).cuda()
+    seed = torch.zeros(inst.K, inst.storage.S, device="cuda")
+    seed[:, 0] = 1.0 / inst.K
+    res = {}
+    for every in (0, 16):
+        def value_only():
+            if every:
+                return dp.solve(lam, P, inst.storage, store_all=False, policy=False, ckpt_every=every)
+            return dp.solve(lam, P, inst.storage, store_all=True, policy=True)
+
+        def value_and_adjoint():
+            out = value_only()
+            if every:
+                dp.adjoint(lam, P, inst.storage, seed, ckpt=out["ckpt"], ckpt_every=every)
+            else:
+                dp.adjoint(lam, P, inst.storage, seed, V_all=out["V"], policy=out["policy"])
+
+        for f in (value_only, value_and_adjoint):
+            f()
+        torch.cuda.synchronize()
+        tv = []
+        for f in (value_only, value_and_adjoint):
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                f()
+            torch.cuda.synchronize()
+            tv.append((time.perf_counter() - t0) / reps)
+        res["ckpt16" if every else "full_storage"] = {
+            "value_ms": round(tv[0] * 1e3, 3), "value_adjoint_ms": round(tv[1] * 1e3, 3),
+            "ratio": round(tv[1] / tv[0], 3)}
+    return res
+
+
+def batch_compare(dp, torch, reps=2):
+    import workloads as wl
+    insts = wl.fleet_5min()
+    try:
+        plan = dp.BatchPlan([(i.T, i.K, i.storage) for i in insts])
+    except dp.DPError as e:
+        return {"skipped": str(e)}
+    cache = {}
+    lams, Ps, V1s, pols = [], [], [], []
+    for i in insts:
+        lams.append(torch.from_numpy(i.lam).cuda())
+        key = id(i.P)
+        if key not in cache:
+            cache[key] = torch.from_numpy(i.P).cuda()
+        Ps.append(cache[key])
+        V1s.append(torch.empty(i.K, i.storage.S, device="cuda"))
+        pols.append(torch.empty(i.T, i.K, i.storage.S, dtype=torch.int16, device="cuda"))
+    cand = sum(i.candidates() for i in insts)
+    out = {"instances": len(insts), "candidates": cand}
+    for looped in (False, True):
+        plan.solve(lams, Ps, V1s, pols, looped=looped)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            plan.solve(lams, Ps, V1s, pols, looped=looped)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        out["looped" if looped else "batched"] = {"ms": round(dt * 1e3, 2),
+                                                  "Gupd_per_s": round(cand / dt / 1e9, 1)}
+    out["speedup"] = round(out["looped"]["ms"] / out["batched"]["ms"], 3)
+    plan.close()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="day_5min")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build solves on one GPU only (asked for {args.gpus}); the "
+              "multi-GPU sharding of the batched solve is described in DESIGN.md",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as wl
+    import paper_2511_15629_amd as dp
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    inst = wl.WORKLOADS[args.workload]()
+    sec, timing = timed_solves(dp, torch, inst, args.steps, args.warmup)
+    cand = inst.candidates()
+    st = inst.storage
+    line = {
+        "metric": "DP state-action updates/s", "value": round(cand / sec, 1), "unit": "updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(sec * 1e3, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": inst.name, "T": inst.T, "K": inst.K, "S": st.S,
+                   "w_up": st.w_up, "w_down": st.w_down, "candidates_per_step": cand,
+                   "outputs": "V_1 f32 + all int16 policies", "parallelism": "single GPU"},
+        "roofline": roofline_of(inst, timing),
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(inst)
+    if not args.no_extra:
+        extra = {}
+        year = wl.year_hourly()
+        ysec, ytim = timed_solves(dp, torch, year, 2, 1)
+        extra["year_hourly"] = {"workload": year.name, "ms": round(ysec * 1e3, 2),
+                                "updates_per_s": round(year.candidates() / ysec, 1),
+                                "roofline": roofline_of(year, ytim)}
+        del year
+        extra["adjoint_vs_value"] = adjoint_ratio(dp, torch, wl.day_5min_adjoint())
+        extra["batched_vs_looped"] = batch_compare(dp, torch)
+        line["extra"] = extra
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

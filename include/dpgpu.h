@@ -1,0 +1,182 @@
+/*
+ * dpgpu -- MI355X (gfx950) backward induction for multistage stochastic storage
+ * arbitrage on a Markov price chain.  C ABI of libdpgpu.so.
+ *
+ * The method (T. Lee, A. Sun, "GPU-Accelerated Dynamic Programming for Multistage
+ * Stochastic Energy Storage Arbitrage"):
+ *   - storage model: Sec. II-A, Eq. (1) objective sum_t lambda_t p_t, Eq. (2) state
+ *     transition F (charging raises the state of charge by eta |p|, discharging lowers it
+ *     by p / eta);
+ *   - feasible actions: Eq. (4), discretised on the recombining grid of Sec. III-A, where
+ *     every interior power action moves the state of charge by a whole number of steps;
+ *   - Bellman recursion: Eq. (5)-(6) with the terminal value of Eq. (6) (zero unless given);
+ *   - tensor backward induction: Algorithm 1 (next-state gather, -inf mask of infeasible
+ *     pairs, payoff tensor, max over actions, expectation).
+ * This library generalises the expectation of Algorithm 1 from independent price samples
+ * to a Markov chain with per-stage transition matrices P_t (the independent case is the
+ * special case where every row of P_t is the next stage's probability vector).
+ *
+ * Indexing (0-based): stage t = 1..T is array slice t-1; price state k in [0, K);
+ * state-of-charge index s in [0, S) meaning energy s * delta.  A move to next index j
+ * is feasible iff max(0, s - w_down) <= j <= min(S - 1, s + w_up).  It sells
+ *   g(d) = -d * delta / eta_c   (d = j - s > 0, charging),
+ *   g(d) = -d * delta * eta_d   (d < 0, discharging),   g(0) = 0    [MWh]
+ * and earns r(lambda, d) = lambda * g(d) - c_deg * |g(d)| - c_start * [d != 0]  [$].
+ * For every stage, price state k and index s the library computes
+ *   W_t[k][j] = sum_{k'} P_t[k][k'] * V_{t+1}[k'][j]                  (expectation),
+ *   V_t[k][s] = max_{feasible j} r(lam_t[k], j - s) + W_t[k][j]        (Bellman max),
+ *   policy_t[k][s] = smallest j attaining the max                    (argmax),
+ * in FP32 arithmetic with FP32 accumulation.
+ *
+ * Memory: every array argument is DEVICE memory owned by the caller unless stated
+ * otherwise; arrays are dense, row-major, with the shapes given below.  The library
+ * never frees caller memory.  Calls are asynchronous on the given HIP stream (a
+ * hipStream_t passed as void*, NULL = the null stream); device faults surface at the
+ * next synchronisation.  Return value: DP_OK or a negative DP_E* code; dp_last_error()
+ * gives a thread-local description of the last failure.  No exception or abort crosses
+ * this interface.
+ */
+#ifndef DPGPU_H
+#define DPGPU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DPGPU_ABI_VERSION 1
+
+/* Error codes. */
+#define DP_OK        0
+#define DP_EINVAL   -1   /* bad dimension, pointer or parameter (checked on the host)   */
+#define DP_EBADPROB -2   /* transition rows not stochastic (only with DP_VALIDATE)       */
+#define DP_ENOWS    -3   /* workspace missing or smaller than the *_workspace_bytes()    */
+#define DP_EHIP     -4   /* a HIP runtime call failed                                    */
+#define DP_ETIMEOUT -5   /* a persistent kernel's bounded wait expired                   */
+#define DP_ENOMEM   -6   /* host allocation failed (plans only)                          */
+#define DP_ENOTSUP  -7   /* valid request outside what this build supports               */
+
+/* Limits. */
+#define DP_MAX_S 32767   /* next-state indices are stored as int16                       */
+#define DP_MAX_K 1024
+
+/* Flags of dp_problem.flags. */
+#define DP_STORE_V_ALL 0x1u  /* V output holds all stages [T+1][K][S] (else V_1 [K][S])   */
+#define DP_VALIDATE    0x2u  /* check P >= 0 and |row sum - 1| <= 1e-6 before solving     */
+
+/* Battery on the state-of-charge grid (Sec. III-A): S points 0, delta, ..., (S-1) delta;
+ * per-stage move limits w_up (charging) and w_down (discharging) in grid steps. */
+typedef struct dp_storage {
+    int32_t S;        /* 2 .. DP_MAX_S                                              */
+    int32_t w_up;     /* >= 0                                                       */
+    int32_t w_down;   /* >= 0                                                       */
+    int32_t reserved; /* must be 0                                                  */
+    float delta;      /* MWh per grid step, > 0                                     */
+    float eta_c;      /* charging efficiency, (0, 1]                                */
+    float eta_d;      /* discharging efficiency, (0, 1]                             */
+    float c_deg;      /* $ per MWh of grid-side throughput |g|, >= 0                */
+    float c_start;    /* $ per stage with a non-zero move, >= 0                     */
+} dp_storage;
+
+typedef struct dp_problem {
+    int32_t T;           /* stages, >= 1                                           */
+    int32_t K;           /* price states, 1 .. DP_MAX_K                            */
+    dp_storage st;
+    uint32_t flags;      /* DP_STORE_V_ALL | DP_VALIDATE                           */
+    int32_t ckpt_every;  /* stages between value checkpoints (>= 1); used by
+                            dp_ckpt_bytes / dp_solve(ckpt != NULL) / dp_adjoint     */
+} dp_problem;
+
+int dp_abi_version(void);
+const char *dp_strerror(int code);
+const char *dp_last_error(void);
+
+/* Tuning hook: force the Bellman-sweep tile shape for later solves in this process --
+ * R outputs per lane, D moves per chunk, NW waves per block, NSPLIT blocks of the move
+ * range (NW % NSPLIT == 0).  R = 0 restores the built-in choice.  The shape never changes
+ * results: every shape yields bitwise the same values and policies.  DP_EINVAL for a
+ * shape this build has no kernel for.  Not thread-safe with concurrent solves. */
+int dp_set_sweep_shape(int R, int D, int NW, int NSPLIT);
+
+/* Measurement hook: while on, dp_solve records a pair of HIP events on its stream around
+ * every Bellman-sweep launch and every expectation launch.  dp_get_timing waits for the
+ * recorded events, returns the summed elapsed milliseconds and launch counts of each
+ * kind since the last call (or since dp_set_timing), and resets the record.  Host-side
+ * state of this process; not thread-safe with concurrent solves. */
+int dp_set_timing(int on);
+int dp_get_timing(double *sweep_ms, int *n_sweep, double *expect_ms, int *n_expect);
+
+/* Bytes of device workspace dp_solve needs (0 on invalid input). */
+size_t dp_workspace_bytes(const dp_problem *pb);
+
+/* Bytes of the checkpoint buffer: the solver's internal value state (FP32 values
+ * relative to an FP64 per-stage offset) at stages 1 + m * ckpt_every, m >= 1, that
+ * lie in [2, T].  Opaque layout; only dp_adjoint reads it. */
+size_t dp_ckpt_bytes(const dp_problem *pb);
+
+/* Backward induction t = T..1 (Eq. (5)-(6), Algorithm 1 with a Markov expectation).
+ *   lam     [T][K]     price level of state k at stage t ($/MWh)
+ *   P       [T][K][K]  P_t[k][k'] = Pr(state k' at t+1 | state k at t); row k sums to 1
+ *   v_term  [K][S]     value of ending in (k, s) after stage T; NULL means 0
+ *   V       out: [T+1][K][S] (DP_STORE_V_ALL; slice T is v_term) or [K][S] (V_1 only)
+ *   policy  out: [T][K][S] int16 next-state index j, or NULL
+ *   ckpt    out: dp_ckpt_bytes(pb) bytes for a later dp_adjoint, or NULL
+ *   ws      workspace of at least dp_workspace_bytes(pb) bytes, 256-byte aligned */
+int dp_solve(const dp_problem *pb, const float *lam, const float *P, const float *v_term,
+             float *V, int16_t *policy, void *ckpt, void *ws, size_t ws_bytes, void *stream);
+
+/* Bytes of device workspace dp_adjoint needs. */
+size_t dp_adjoint_workspace_bytes(const dp_problem *pb);
+
+/* Adjoint of J = sum_{k,s} seed[k][s] V_1[k][s] for the policies of the forward solve
+ * (exact wherever the argmax is unique).  Runs forward in time: the occupation measure
+ * mu_1 = seed is pushed through the stored policy of each stage, then through P_t:
+ *   grad_lam[t][k]   = sum_s mu_t[k][s] g(policy_t[k][s] - s)
+ *   nu_t[k][j]       = sum_{s: policy_t[k][s] = j} mu_t[k][s]
+ *   grad_P[t][k][k'] = sum_j nu_t[k][j] V_{t+1}[k'][j]
+ *   mu_{t+1}         = P_t^T nu_t ;   grad_vterm = mu_{T+1}.
+ * Inputs: either (V_all [T+1][K][S] and policy [T][K][S]) from dp_solve with
+ * DP_STORE_V_ALL, or ckpt from dp_solve(ckpt != NULL) with V_all = policy = NULL, in
+ * which case every segment of ckpt_every stages is recomputed from its checkpoint
+ * (bitwise the same values and policies as the forward solve).
+ *   seed [K][S]; outputs grad_lam [T][K], grad_P [T][K][K], grad_vterm [K][S] (or NULL).
+ * Requires S <= 8192. */
+int dp_adjoint(const dp_problem *pb, const float *lam, const float *P, const float *v_term,
+               const float *V_all, const int16_t *policy, const void *ckpt,
+               const float *seed, float *grad_lam, float *grad_P, float *grad_vterm,
+               void *ws, size_t ws_bytes, void *stream);
+
+/* Batched solves of many independent instances in one persistent launch.
+ * A plan owns a device work table, its device workspace and a captured HIP graph; it
+ * is created once for a fixed list of problems (host array probs[n]) and replayed with
+ * new data.  tune_cache: path of a text cache of autotuned tile shapes (created or
+ * extended), or NULL to use built-in defaults without tuning. */
+typedef struct dp_batch_plan dp_batch_plan;
+
+int dp_batch_plan_create(dp_batch_plan **out, int n, const dp_problem *probs,
+                         const char *tune_cache, void *stream);
+
+/* Solve every instance i: lam[i] [T_i][K_i], P[i] [T_i][K_i][K_i] (device pointers held
+ * in HOST arrays of length n), outputs V1[i] [K_i][S_i] and policy[i] [T_i][K_i][S_i]
+ * (policy[i] may be NULL for all i or none).  Terminal values are zero.  The first call
+ * captures a graph keyed on the pointer set; later calls with the same pointers replay
+ * it, new pointers re-capture. */
+int dp_batch_solve(dp_batch_plan *plan, const float *const *lam, const float *const *P,
+                   float *const *V1, int16_t *const *policy, void *stream);
+
+/* Same batch, one ordinary dp_solve per instance on the stream (for comparison). */
+int dp_batch_solve_looped(dp_batch_plan *plan, const float *const *lam,
+                          const float *const *P, float *const *V1,
+                          int16_t *const *policy, void *stream);
+
+/* Description of the plan's tile choices: writes a NUL-terminated text into buf. */
+int dp_batch_plan_describe(const dp_batch_plan *plan, char *buf, size_t len);
+
+void dp_batch_plan_destroy(dp_batch_plan *plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DPGPU_H */

@@ -1,0 +1,191 @@
+"""dpgpu: MI355X backward induction for stochastic storage arbitrage (Python binding).
+
+Thin layer over libdpgpu.so (see include/dpgpu.h).  PyTorch supplies device memory
+and the current HIP stream; every step of the computation runs in the library's HIP
+kernels.
+
+    out = solve(lam, P, storage)                 # V_1 [K, S] float32, policy [T, K, S] int16
+    V1 = DPFunction.apply(lam, P, storage, 16)   # differentiable in lam and P
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import torch
+
+from . import _lib
+from ._lib import DPError, DP_STORE_V_ALL, DP_VALIDATE, check, lib, make_problem
+
+__all__ = ["solve", "adjoint", "Solver", "DPFunction", "DPError", "set_sweep_shape",
+           "BatchPlan", "kernel_timing"]
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_f32(x, name):
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if x.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32")
+    return x.contiguous()
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    # torch's caching allocator returns blocks aligned to at least 512 bytes
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def set_sweep_shape(R: int = 0, D: int = 0, NW: int = 0, NSPLIT: int = 0):
+    """Force the sweep tile shape (tuning hook); no arguments restores the default."""
+    check(lib().dp_set_sweep_shape(R, D, NW, NSPLIT))
+
+
+def kernel_timing(on: Optional[bool] = None):
+    """With on=True/False switch the library's per-launch event timing; with no argument
+    return and reset (sweep_ms, n_sweep, expectation_ms, n_expectation)."""
+    L = lib()
+    if on is not None:
+        check(L.dp_set_timing(1 if on else 0))
+        return None
+    a, b = ctypes.c_double(), ctypes.c_double()
+    na, nb = ctypes.c_int(), ctypes.c_int()
+    check(L.dp_get_timing(ctypes.byref(a), ctypes.byref(na), ctypes.byref(b), ctypes.byref(nb)))
+    return a.value, na.value, b.value, nb.value
+
+
+class Solver:
+    """Reusable solve: problem record, workspace and outputs allocated once, so repeated
+    calls (benchmarks, serving loops) allocate nothing."""
+
+    def __init__(self, lam: torch.Tensor, P: torch.Tensor, storage, *, store_all=False,
+                 policy=True, ckpt_every=0):
+        self.lam = _dev_f32(lam, "lam")
+        self.P = _dev_f32(P, "P")
+        T, K = self.lam.shape
+        if tuple(self.P.shape) != (T, K, K):
+            raise ValueError("P must be [T, K, K]")
+        S = int(storage.S)
+        self.pb = make_problem(T, K, storage, DP_STORE_V_ALL if store_all else 0, ckpt_every)
+        L = lib()
+        dev = self.lam.device
+        self.V = torch.empty((T + 1, K, S) if store_all else (K, S), dtype=torch.float32,
+                             device=dev)
+        self.policy = torch.empty((T, K, S), dtype=torch.int16, device=dev) if policy else None
+        self.ckpt = _workspace(L.dp_ckpt_bytes(ctypes.byref(self.pb)), dev) if ckpt_every else None
+        nws = L.dp_workspace_bytes(ctypes.byref(self.pb))
+        if nws == 0:
+            check(_lib.DP_EINVAL)
+        self.ws = _workspace(nws, dev)
+
+    def run(self, v_term: Optional[torch.Tensor] = None, stream=None):
+        check(lib().dp_solve(ctypes.byref(self.pb), _ptr(self.lam), _ptr(self.P), _ptr(v_term),
+                             _ptr(self.V), _ptr(self.policy), _ptr(self.ckpt), _ptr(self.ws),
+                             ctypes.c_size_t(self.ws.numel()), _stream(stream)))
+        return self.V
+
+
+def solve(lam: torch.Tensor, P: torch.Tensor, storage, v_term: Optional[torch.Tensor] = None,
+          *, store_all: bool = False, policy: bool = True, ckpt_every: int = 0,
+          validate: bool = False, stream=None):
+    """Backward induction on the GPU.
+
+    lam [T, K], P [T, K, K] float32 device tensors; storage has S, w_up, w_down, delta,
+    eta_c, eta_d, c_deg, c_start.  Returns a dict with ``V`` ([T+1, K, S] if store_all
+    else V_1 [K, S]), ``policy`` ([T, K, S] int16 or None), ``ckpt`` (uint8 buffer or None)
+    and the problem record.
+    """
+    lam = _dev_f32(lam, "lam")
+    P = _dev_f32(P, "P")
+    T, K = lam.shape
+    if tuple(P.shape) != (T, K, K):
+        raise ValueError(f"P must have shape {(T, K, K)}, got {tuple(P.shape)}")
+    S = int(storage.S)
+    flags = (DP_STORE_V_ALL if store_all else 0) | (DP_VALIDATE if validate else 0)
+    pb = make_problem(T, K, storage, flags, ckpt_every)
+    L = lib()
+    dev = lam.device
+    if v_term is not None:
+        v_term = _dev_f32(v_term, "v_term")
+        if tuple(v_term.shape) != (K, S):
+            raise ValueError("v_term must be [K, S]")
+    V = torch.empty((T + 1, K, S) if store_all else (K, S), dtype=torch.float32, device=dev)
+    pol = torch.empty((T, K, S), dtype=torch.int16, device=dev) if policy else None
+    ck = None
+    if ckpt_every:
+        ck = _workspace(L.dp_ckpt_bytes(ctypes.byref(pb)), dev)
+    nws = L.dp_workspace_bytes(ctypes.byref(pb))
+    if nws == 0:
+        check(_lib.DP_EINVAL)
+    ws = _workspace(nws, dev)
+    check(L.dp_solve(ctypes.byref(pb), _ptr(lam), _ptr(P), _ptr(v_term), _ptr(V), _ptr(pol),
+                     _ptr(ck), _ptr(ws), ctypes.c_size_t(ws.numel()), _stream(stream)))
+    return {"V": V, "policy": pol, "ckpt": ck, "problem": pb, "_ws": ws}
+
+
+def adjoint(lam, P, storage, seed, *, V_all=None, policy=None, ckpt=None, ckpt_every: int = 0,
+            v_term=None, want_vterm: bool = False, stream=None):
+    """Gradients of J = sum(seed * V_1) w.r.t. lam [T, K], P [T, K, K] (and v_term)."""
+    lam = _dev_f32(lam, "lam")
+    P = _dev_f32(P, "P")
+    seed = _dev_f32(seed, "seed")
+    T, K = lam.shape
+    S = int(storage.S)
+    pb = make_problem(T, K, storage, 0, ckpt_every if ckpt is not None else 0)
+    L = lib()
+    dev = lam.device
+    g_lam = torch.empty((T, K), dtype=torch.float32, device=dev)
+    g_P = torch.empty((T, K, K), dtype=torch.float32, device=dev)
+    g_v = torch.empty((K, S), dtype=torch.float32, device=dev) if want_vterm else None
+    ws = _workspace(L.dp_adjoint_workspace_bytes(ctypes.byref(pb)), dev)
+    if v_term is not None:
+        v_term = _dev_f32(v_term, "v_term")
+    check(L.dp_adjoint(ctypes.byref(pb), _ptr(lam), _ptr(P), _ptr(v_term),
+                       _ptr(V_all), _ptr(policy), _ptr(ckpt), _ptr(seed), _ptr(g_lam),
+                       _ptr(g_P), _ptr(g_v), _ptr(ws), ctypes.c_size_t(ws.numel()),
+                       _stream(stream)))
+    return {"grad_lam": g_lam, "grad_P": g_P, "grad_vterm": g_v}
+
+
+class DPFunction(torch.autograd.Function):
+    """V_1 = DP(lam, P) with a hand-written adjoint.
+
+    forward(lam [T,K], P [T,K,K], storage, ckpt_every=0) -> V_1 [K, S].
+    ckpt_every = 0 keeps all stage values and int16 policies for the backward pass;
+    ckpt_every = n keeps value checkpoints every n stages and recomputes each segment's
+    values and policies in backward (bitwise the same as the forward pass).
+    The gradient is exact for the fixed argmax policies (almost everywhere).
+    """
+
+    @staticmethod
+    def forward(ctx, lam, P, storage, ckpt_every: int = 0):
+        if ckpt_every:
+            out = solve(lam, P, storage, store_all=False, policy=False, ckpt_every=ckpt_every)
+            ctx.save_for_backward(lam, P, out["ckpt"])
+        else:
+            out = solve(lam, P, storage, store_all=True, policy=True)
+            ctx.save_for_backward(lam, P, out["V"], out["policy"])
+        ctx.storage = storage
+        ctx.ckpt_every = ckpt_every
+        return out["V"][0].clone() if not ckpt_every else out["V"]
+
+    @staticmethod
+    def backward(ctx, grad_V1):
+        seed = grad_V1.contiguous().to(torch.float32)
+        if ctx.ckpt_every:
+            lam, P, ck = ctx.saved_tensors
+            g = adjoint(lam, P, ctx.storage, seed, ckpt=ck, ckpt_every=ctx.ckpt_every)
+        else:
+            lam, P, V_all, pol = ctx.saved_tensors
+            g = adjoint(lam, P, ctx.storage, seed, V_all=V_all, policy=pol)
+        return g["grad_lam"], g["grad_P"], None, None
+
+
+from .batch import BatchPlan  # noqa: E402

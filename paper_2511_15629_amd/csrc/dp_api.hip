@@ -1,0 +1,448 @@
+// Host side of libdpgpu: argument validation, workspace layout, the stage loop of the
+// backward induction and the forward-in-time adjoint driver.  See include/dpgpu.h.
+#include "dpgpu.h"
+#include "dp_internal.h"
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(DP_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+dpk::SweepShape g_shape_override = {0, 0, 0, 0};
+
+// Optional per-kernel timing (dp_set_timing): HIP events recorded on the caller's stream
+// around every sweep and expectation launch of dp_solve.
+struct KernelTimer {
+    bool on = false;
+    std::vector<hipEvent_t> ev;      // pairs (start, stop)
+    std::vector<int> kind;           // 0 = sweep, 1 = expectation
+    size_t used = 0;
+} g_timer;
+
+hipError_t timer_mark(hipStream_t s, int kind, bool start)
+{
+    if (!g_timer.on) return hipSuccess;
+    if (start) {
+        if (g_timer.used + 2 > g_timer.ev.size()) {
+            for (int i = 0; i < 256; ++i) {
+                hipEvent_t e;
+                hipError_t r = hipEventCreate(&e);
+                if (r != hipSuccess) return r;
+                g_timer.ev.push_back(e);
+            }
+        }
+        g_timer.kind.push_back(kind);
+    }
+    return hipEventRecord(g_timer.ev[g_timer.used++], s);
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+inline int pad64(int x) { return (x + 63) & ~63; }
+
+}  // namespace
+
+namespace dpgpu {
+
+int validate_problem(const dp_problem *pb)
+{
+    if (!pb) return fail(DP_EINVAL, "problem pointer is NULL");
+    const dp_storage &st = pb->st;
+    if (pb->T < 1) return fail(DP_EINVAL, "T must be >= 1 (got %d)", pb->T);
+    if (pb->K < 1 || pb->K > DP_MAX_K) return fail(DP_EINVAL, "K must be in [1, %d] (got %d)", DP_MAX_K, pb->K);
+    if (st.S < 2 || st.S > DP_MAX_S) return fail(DP_EINVAL, "S must be in [2, %d] (got %d)", DP_MAX_S, st.S);
+    if (st.w_up < 0 || st.w_down < 0) return fail(DP_EINVAL, "move windows must be >= 0");
+    if (st.reserved != 0) return fail(DP_EINVAL, "dp_storage.reserved must be 0");
+    if (!(st.delta > 0.0f) || !isfinite(st.delta)) return fail(DP_EINVAL, "delta must be finite and > 0");
+    if (!(st.eta_c > 0.0f && st.eta_c <= 1.0f)) return fail(DP_EINVAL, "eta_c must be in (0, 1]");
+    if (!(st.eta_d > 0.0f && st.eta_d <= 1.0f)) return fail(DP_EINVAL, "eta_d must be in (0, 1]");
+    if (!(st.c_deg >= 0.0f) || !isfinite(st.c_deg)) return fail(DP_EINVAL, "c_deg must be finite and >= 0");
+    if (!(st.c_start >= 0.0f) || !isfinite(st.c_start)) return fail(DP_EINVAL, "c_start must be finite and >= 0");
+    if (pb->flags & ~(uint32_t)(DP_STORE_V_ALL | DP_VALIDATE)) return fail(DP_EINVAL, "unknown flag bits 0x%x", pb->flags);
+    if (pb->ckpt_every < 0) return fail(DP_EINVAL, "ckpt_every must be >= 0");
+    return DP_OK;
+}
+
+dpk::SweepShape pick_shape(const dp_problem *pb)
+{
+    if (g_shape_override.R) return g_shape_override;
+    const int span = pb->st.w_up + pb->st.w_down + 1;
+    // Long move ranges: 8 outputs per lane, the range split over 8 waves (measured best
+    // on the 100 x 1001 and 50 x 2001 grids); short ranges: fewer splits.
+    if (span >= 256) return dpk::SweepShape{8, 16, 8, 8};
+    if (span >= 64) return dpk::SweepShape{4, 16, 4, 4};
+    return dpk::SweepShape{4, 8, 4, 2};
+}
+
+struct SolveLayout {
+    int Spad;
+    size_t vA, vB, W, off, flag, total;
+};
+
+SolveLayout solve_layout(const dp_problem *pb)
+{
+    SolveLayout L;
+    L.Spad = pad64(pb->st.S);
+    const size_t plane = align256(sizeof(float) * (size_t)pb->K * L.Spad);
+    size_t o = 0;
+    L.vA = o; o += plane;
+    L.vB = o; o += plane;
+    L.W = o; o += plane;
+    L.off = o; o += align256(sizeof(double) * ((size_t)pb->T + 2));
+    L.flag = o; o += 256;
+    L.total = o;
+    return L;
+}
+
+int n_ckpt_slots(const dp_problem *pb)
+{
+    const int E = pb->ckpt_every > 0 ? pb->ckpt_every : 16;
+    // slots m = 1 .. M-1 hold stage 1 + m E (<= T)
+    return (pb->T - 1) / E;
+}
+
+size_t ckpt_bytes(const dp_problem *pb)
+{
+    const int M = n_ckpt_slots(pb);
+    return align256(sizeof(float) * (size_t)M * pb->K * pb->st.S) + align256(sizeof(double) * (size_t)(M > 0 ? M : 1));
+}
+
+// Backward induction over stages [t_lo, t_hi] (1-based) of the problem.  The terminal
+// state (stage t_hi + 1) is v_src (absolute v_term or a normalised checkpoint) with
+// offset *off_src (device pointer or NULL = 0).  Values at stage t are written to
+// vabs_at(t) if non-null; policies to pol + (t - t_lo) K S.
+struct StageOutputs {
+    float *vall;         // [(t_hi - t_lo + 2)][K][S] absolute values, slice t - t_lo (nullable)
+    float *v1;           // [K][S] absolute values of stage t_lo (nullable)
+    int16_t *pol;        // [(t_hi - t_lo + 1)][K][S] (nullable)
+    float *ckpt_v;       // checkpoint slots (nullable)
+    double *ckpt_off;
+    int ckpt_every;
+};
+
+int run_stages(const dp_problem *pb, int t_lo, int t_hi, const float *lam, const float *P,
+               const float *v_src, const double *off_src, const StageOutputs &out, void *ws,
+               hipStream_t stream)
+{
+    const int K = pb->K, S = pb->st.S;
+    const SolveLayout L = solve_layout(pb);
+    char *base = static_cast<char *>(ws);
+    float *vbuf[2] = {reinterpret_cast<float *>(base + L.vA), reinterpret_cast<float *>(base + L.vB)};
+    float *Wb = reinterpret_cast<float *>(base + L.W);
+    double *off = reinterpret_cast<double *>(base + L.off);   // off[t] = C_t, t = t_lo..t_hi+1
+    const size_t KS = (size_t)K * S;
+    const int nst = t_hi - t_lo + 1;
+
+    float *vabs_term = out.vall ? out.vall + (size_t)nst * KS : nullptr;
+    hipError_t e = dpk::launch_init_terminal(v_src, off_src, K, S, vbuf[0], L.Spad,
+                                             off + (t_hi + 1), vabs_term, stream);
+    if (e != hipSuccess) return hip_fail(e, "init_terminal");
+
+    const dpk::SweepShape sh = pick_shape(pb);
+    if (!dpk::sweep_shape_supported(sh)) return fail(DP_EINVAL, "unsupported sweep shape");
+    if (dpk::sweep_lds_bytes(sh, pb->st.w_up, pb->st.w_down) > 160 * 1024)
+        return fail(DP_ENOTSUP, "move window %d..%d needs more LDS than a CU holds",
+                    -pb->st.w_down, pb->st.w_up);
+    dpk::SweepArgs a;
+    a.ldw = L.Spad;
+    a.K = K;
+    a.S = S;
+    a.w_up = pb->st.w_up;
+    a.w_down = pb->st.w_down;
+    a.pay = {pb->st.delta, pb->st.eta_c, pb->st.eta_d, pb->st.c_deg, pb->st.c_start};
+    a.W = Wb;
+    a.ldv = L.Spad;
+    const int E = out.ckpt_every > 0 ? out.ckpt_every : 16;
+    int cur = 0;
+    for (int t = t_hi; t >= t_lo; --t) {
+        const float *vin = vbuf[cur];
+        float *vout = vbuf[cur ^ 1];
+        if ((e = timer_mark(stream, 1, true)) != hipSuccess) return hip_fail(e, "timer");
+        e = dpk::launch_contract(P + (size_t)(t - 1) * K * K, false, vin, L.Spad, Wb, L.Spad, K,
+                                 S, stream);
+        if (e != hipSuccess) return hip_fail(e, "contract");
+        if ((e = timer_mark(stream, 1, false)) != hipSuccess) return hip_fail(e, "timer");
+        a.lam = lam + (size_t)(t - 1) * K;
+        a.vprev = vin;
+        a.off_next = off + (t + 1);
+        a.off_cur = off + t;
+        a.vnorm = vout;
+        a.vabs = out.vall ? out.vall + (size_t)(t - t_lo) * KS : (t == t_lo ? out.v1 : nullptr);
+        a.pol = out.pol ? out.pol + (size_t)(t - t_lo) * KS : nullptr;
+        a.ckpt_v = nullptr;
+        a.ckpt_off = nullptr;
+        if (out.ckpt_v && t >= 2 && (t - 1) % E == 0) {
+            const int m = (t - 1) / E;   // slot m holds stage 1 + m E
+            a.ckpt_v = out.ckpt_v + (size_t)(m - 1) * KS;
+            a.ckpt_off = out.ckpt_off + (m - 1);
+        }
+        if ((e = timer_mark(stream, 0, true)) != hipSuccess) return hip_fail(e, "timer");
+        e = dpk::launch_sweep(a, sh, stream);
+        if (e != hipSuccess) return hip_fail(e, "sweep");
+        if ((e = timer_mark(stream, 0, false)) != hipSuccess) return hip_fail(e, "timer");
+        cur ^= 1;
+    }
+    return DP_OK;
+}
+
+void ckpt_pointers(const dp_problem *pb, void *ckpt, float **cv, double **co)
+{
+    const int M = n_ckpt_slots(pb);
+    char *b = static_cast<char *>(ckpt);
+    *cv = reinterpret_cast<float *>(b);
+    *co = reinterpret_cast<double *>(b + align256(sizeof(float) * (size_t)M * pb->K * pb->st.S));
+}
+
+}  // namespace dpgpu
+
+using namespace dpgpu;
+
+extern "C" {
+
+int dp_abi_version(void) { return DPGPU_ABI_VERSION; }
+
+const char *dp_strerror(int code)
+{
+    switch (code) {
+    case DP_OK: return "success";
+    case DP_EINVAL: return "invalid argument";
+    case DP_EBADPROB: return "transition rows are not stochastic";
+    case DP_ENOWS: return "workspace missing or too small";
+    case DP_EHIP: return "HIP runtime error";
+    case DP_ETIMEOUT: return "persistent kernel wait timed out";
+    case DP_ENOMEM: return "host allocation failed";
+    case DP_ENOTSUP: return "not supported by this build";
+    default: return "unknown error";
+    }
+}
+
+const char *dp_last_error(void) { return g_last_error.c_str(); }
+
+// Tuning hook: force the sweep tile shape (R outputs per lane, D moves per chunk, NW waves
+// per block, NSPLIT move splits); R = 0 restores the built-in choice.
+int dp_set_sweep_shape(int R, int D, int NW, int NSPLIT)
+{
+    dpk::SweepShape sh = {R, D, NW, NSPLIT};
+    if (R == 0) {
+        g_shape_override = sh;
+        return DP_OK;
+    }
+    if (!dpk::sweep_shape_supported(sh)) return fail(DP_EINVAL, "unsupported sweep shape %d,%d,%d,%d", R, D, NW, NSPLIT);
+    g_shape_override = sh;
+    return DP_OK;
+}
+
+int dp_set_timing(int on)
+{
+    g_timer.on = on != 0;
+    g_timer.used = 0;
+    g_timer.kind.clear();
+    return DP_OK;
+}
+
+int dp_get_timing(double *sweep_ms, int *n_sweep, double *expect_ms, int *n_expect)
+{
+    double t[2] = {0.0, 0.0};
+    int n[2] = {0, 0};
+    for (size_t i = 0; 2 * i + 1 < g_timer.used; ++i) {
+        hipError_t e = hipEventSynchronize(g_timer.ev[2 * i + 1]);
+        if (e != hipSuccess) return hip_fail(e, "timing sync");
+        float ms = 0.0f;
+        e = hipEventElapsedTime(&ms, g_timer.ev[2 * i], g_timer.ev[2 * i + 1]);
+        if (e != hipSuccess) return hip_fail(e, "timing elapsed");
+        const int k = g_timer.kind[i];
+        t[k] += ms;
+        n[k] += 1;
+    }
+    if (sweep_ms) *sweep_ms = t[0];
+    if (n_sweep) *n_sweep = n[0];
+    if (expect_ms) *expect_ms = t[1];
+    if (n_expect) *n_expect = n[1];
+    g_timer.used = 0;
+    g_timer.kind.clear();
+    return DP_OK;
+}
+
+size_t dp_workspace_bytes(const dp_problem *pb)
+{
+    if (validate_problem(pb) != DP_OK) return 0;
+    return solve_layout(pb).total;
+}
+
+size_t dp_ckpt_bytes(const dp_problem *pb)
+{
+    if (validate_problem(pb) != DP_OK) return 0;
+    if (pb->ckpt_every < 1) return 0;
+    return ckpt_bytes(pb);
+}
+
+int dp_solve(const dp_problem *pb, const float *lam, const float *P, const float *v_term,
+             float *V, int16_t *policy, void *ckpt, void *ws, size_t ws_bytes, void *stream_)
+{
+    int rc = validate_problem(pb);
+    if (rc != DP_OK) return rc;
+    if (!lam || !P || !V) return fail(DP_EINVAL, "lam, P and V must be non-NULL");
+    if (ckpt && pb->ckpt_every < 1) return fail(DP_EINVAL, "ckpt given but ckpt_every < 1");
+    const SolveLayout L = solve_layout(pb);
+    if (!ws || ws_bytes < L.total) return fail(DP_ENOWS, "workspace needs %zu bytes (got %zu)", L.total, ws_bytes);
+    if (((uintptr_t)ws & 255) != 0) return fail(DP_EINVAL, "workspace must be 256-byte aligned");
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    if (pb->flags & DP_VALIDATE) {
+        int *flag = reinterpret_cast<int *>(static_cast<char *>(ws) + L.flag);
+        int host = 0;
+        hipError_t e = hipMemcpyAsync(flag, &host, sizeof(int), hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) e = dpk::launch_validate_P(P, pb->T, pb->K, flag, stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(&host, flag, sizeof(int), hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return hip_fail(e, "validate P");
+        if (host) return fail(DP_EBADPROB, "a row of P has a negative entry or does not sum to 1");
+    }
+    StageOutputs out = {};
+    const size_t KS = (size_t)pb->K * pb->st.S;
+    if (pb->flags & DP_STORE_V_ALL) out.vall = V;
+    else out.v1 = V;
+    out.pol = policy;
+    out.ckpt_every = pb->ckpt_every;
+    if (ckpt) ckpt_pointers(pb, ckpt, &out.ckpt_v, &out.ckpt_off);
+    (void)KS;
+    return run_stages(pb, 1, pb->T, lam, P, v_term, nullptr, out, ws, stream);
+}
+
+// ------------------------------------------------------------------------------------
+// Adjoint.
+// ------------------------------------------------------------------------------------
+struct AdjLayout {
+    int Spad;
+    size_t mu, nu, vseg, polseg, solve_ws, total;
+};
+
+static AdjLayout adj_layout(const dp_problem *pb, bool ckpt_mode)
+{
+    AdjLayout L = {};
+    L.Spad = pad64(pb->st.S);
+    const size_t plane = align256(sizeof(float) * (size_t)pb->K * L.Spad);
+    size_t o = 0;
+    L.mu = o; o += plane;
+    L.nu = o; o += plane;
+    if (ckpt_mode) {
+        const int E = pb->ckpt_every > 0 ? pb->ckpt_every : 16;
+        const size_t KS = (size_t)pb->K * pb->st.S;
+        L.vseg = o; o += align256(sizeof(float) * (size_t)(E + 1) * KS);
+        L.polseg = o; o += align256(sizeof(int16_t) * (size_t)E * KS);
+        L.solve_ws = o; o += solve_layout(pb).total;
+    }
+    L.total = o;
+    return L;
+}
+
+size_t dp_adjoint_workspace_bytes(const dp_problem *pb)
+{
+    if (validate_problem(pb) != DP_OK) return 0;
+    return adj_layout(pb, pb->ckpt_every >= 1).total;
+}
+
+int dp_adjoint(const dp_problem *pb, const float *lam, const float *P, const float *v_term,
+               const float *V_all, const int16_t *policy, const void *ckpt, const float *seed,
+               float *grad_lam, float *grad_P, float *grad_vterm, void *ws, size_t ws_bytes,
+               void *stream_)
+{
+    int rc = validate_problem(pb);
+    if (rc != DP_OK) return rc;
+    const int K = pb->K, S = pb->st.S, T = pb->T;
+    if (S > 8192) return fail(DP_ENOTSUP, "adjoint supports S <= 8192 (got %d)", S);
+    if (!lam || !P || !seed || !grad_lam || !grad_P) return fail(DP_EINVAL, "lam, P, seed, grad_lam, grad_P must be non-NULL");
+    const bool ckpt_mode = (ckpt != nullptr);
+    if (ckpt_mode) {
+        if (V_all || policy) return fail(DP_EINVAL, "give either (V_all, policy) or ckpt, not both");
+        if (pb->ckpt_every < 1) return fail(DP_EINVAL, "ckpt mode needs ckpt_every >= 1");
+    } else if (!V_all || !policy) {
+        return fail(DP_EINVAL, "full-storage mode needs V_all and policy");
+    }
+    const AdjLayout L = adj_layout(pb, ckpt_mode);
+    if (!ws || ws_bytes < L.total) return fail(DP_ENOWS, "adjoint workspace needs %zu bytes (got %zu)", L.total, ws_bytes);
+    if (((uintptr_t)ws & 255) != 0) return fail(DP_EINVAL, "workspace must be 256-byte aligned");
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+    char *base = static_cast<char *>(ws);
+    float *mu = reinterpret_cast<float *>(base + L.mu);
+    float *nu = reinterpret_cast<float *>(base + L.nu);
+    const size_t KS = (size_t)K * S;
+    const dpk::Payoff pay = {pb->st.delta, pb->st.eta_c, pb->st.eta_d, pb->st.c_deg, pb->st.c_start};
+    hipError_t e = dpk::launch_copy_rows(seed, S, mu, L.Spad, K, S, stream);
+    if (e != hipSuccess) return hip_fail(e, "seed copy");
+
+    const int E = ckpt_mode ? pb->ckpt_every : T;
+    float *cv = nullptr;
+    double *co = nullptr;
+    if (ckpt_mode) ckpt_pointers(pb, const_cast<void *>(ckpt), &cv, &co);
+    for (int t_lo = 1; t_lo <= T; t_lo += E) {
+        const int t_hi = t_lo + E - 1 < T ? t_lo + E - 1 : T;
+        const float *Vseg;       // slice (t - t_lo) holds V_t, slice t_hi + 1 - t_lo holds V_{t_hi+1}
+        const int16_t *pseg;
+        if (ckpt_mode) {
+            float *vs = reinterpret_cast<float *>(base + L.vseg);
+            int16_t *ps = reinterpret_cast<int16_t *>(base + L.polseg);
+            const float *src;
+            const double *src_off;
+            if (t_hi == T) {
+                src = v_term;
+                src_off = nullptr;
+            } else {
+                const int m = t_hi / E;          // stage t_hi + 1 = 1 + m E
+                src = cv + (size_t)(m - 1) * KS;
+                src_off = co + (m - 1);
+            }
+            StageOutputs out = {};
+            out.vall = vs;
+            out.pol = ps;
+            out.ckpt_every = E;
+            rc = run_stages(pb, t_lo, t_hi, lam, P, src, src_off, out, base + L.solve_ws, stream);
+            if (rc != DP_OK) return rc;
+            Vseg = vs;
+            pseg = ps;
+        } else {
+            Vseg = V_all + (size_t)(t_lo - 1) * KS;
+            pseg = policy + (size_t)(t_lo - 1) * KS;
+        }
+        for (int t = t_lo; t <= t_hi; ++t) {
+            const int16_t *pol_t = pseg + (size_t)(t - t_lo) * KS;
+            const float *Vn = Vseg + (size_t)(t + 1 - t_lo) * KS;
+            e = dpk::launch_pushforward(mu, L.Spad, pol_t, K, S, pay, nu, L.Spad,
+                                        grad_lam + (size_t)(t - 1) * K, stream);
+            if (e != hipSuccess) return hip_fail(e, "pushforward");
+            e = dpk::launch_gradP(nu, L.Spad, Vn, K, S, grad_P + (size_t)(t - 1) * K * K, stream);
+            if (e != hipSuccess) return hip_fail(e, "gradP");
+            e = dpk::launch_contract(P + (size_t)(t - 1) * K * K, true, nu, L.Spad, mu, L.Spad, K,
+                                     S, stream);
+            if (e != hipSuccess) return hip_fail(e, "transport");
+        }
+    }
+    if (grad_vterm) {
+        e = dpk::launch_copy_rows(mu, L.Spad, grad_vterm, S, K, S, stream);
+        if (e != hipSuccess) return hip_fail(e, "grad_vterm copy");
+    }
+    return DP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,61 @@
+// Internal declarations shared by the kernel and host translation units of libdpgpu.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dpk {
+
+// Payoff parameters of one instance (FP32 on the device).
+struct Payoff {
+    float delta, eta_c, eta_d, c_deg, c_start;
+};
+
+// One stage of the Bellman sweep (Eq. (5)): inputs W_t (expectation) and lam_t,
+// outputs the normalised values, optional absolute values, policies, checkpoint.
+struct SweepArgs {
+    const float *W;          // [K][ldw] expectation W_t
+    int ldw;
+    const float *lam;        // [K]
+    int K, S, w_up, w_down;
+    Payoff pay;
+    const float *vprev;      // normalised V_{t+1} (its [0][0] entry is this stage's shift)
+    const double *off_next;  // C_{t+1}
+    double *off_cur;         // C_t (written by block (0,0))
+    float *vnorm;            // out [K][ldv] normalised V_t = U - shift
+    int ldv;
+    float *vabs;             // out [K][S] absolute V_t (nullable)
+    int16_t *pol;            // out [K][S] (nullable)
+    float *ckpt_v;           // out [K][S] normalised copy (nullable)
+    double *ckpt_off;        // out C_t (nullable)
+};
+
+struct SweepShape {
+    int R, D, NW, NSPLIT;    // outputs per lane, chunk of moves, waves per block, move splits
+};
+
+// Stage kernels (launchers; all asynchronous on `stream`).
+hipError_t launch_contract(const float *A, bool transA, const float *B, int ldb, float *C,
+                           int ldc, int K, int N, hipStream_t stream);
+hipError_t launch_sweep(const SweepArgs &a, const SweepShape &sh, hipStream_t stream);
+int sweep_tile(const SweepShape &sh);       // outputs per block along s
+size_t sweep_lds_bytes(const SweepShape &sh, int w_up, int w_down);
+bool sweep_shape_supported(const SweepShape &sh);
+
+// Initialise the normalised terminal state: vnorm = v_term (or 0, or a checkpoint),
+// off[0] = offset, optional absolute copy into vabs.
+hipError_t launch_init_terminal(const float *src, const double *src_off, int K, int S,
+                                float *vnorm, int ldv, double *off, float *vabs,
+                                hipStream_t stream);
+
+// Adjoint stage kernels.
+hipError_t launch_pushforward(const float *mu, int ldm, const int16_t *pol, int K, int S,
+                              Payoff pay, float *nu, int ldn, float *grad_lam,
+                              hipStream_t stream);
+hipError_t launch_gradP(const float *nu, int ldn, const float *V, int K, int S,
+                        float *gP, hipStream_t stream);
+hipError_t launch_copy_rows(const float *src, int lds, float *dst, int ldd, int K, int S,
+                            hipStream_t stream);
+hipError_t launch_fill(float *dst, size_t n, float v, hipStream_t stream);
+hipError_t launch_validate_P(const float *P, int T, int K, int *flag, hipStream_t stream);
+
+}  // namespace dpk

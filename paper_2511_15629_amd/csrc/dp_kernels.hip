@@ -1,0 +1,512 @@
+// HIP kernels for gfx950 (CDNA4): per-stage expectation on MFMA, max-plus Bellman sweep
+// with argmax on the VALU, and the adjoint stage kernels.
+//
+// Method: backward induction of Eq. (5)-(6) in the tensor form of Algorithm 1, with the
+// expectation generalised to a Markov chain (W_t = P_t V_{t+1}) and the action axis
+// restricted to whole grid steps (the recombining grid of Sec. III-A).
+#include "dp_internal.h"
+
+#include <math.h>
+
+namespace dpk {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------------------------------
+// Payoff of a move of d grid steps (Eq. (1) objective with the transition of Eq. (2)):
+// g(d) MWh sold to the grid, r = lam g - c_deg |g| - c_start [d != 0].
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ float move_energy(int d, const Payoff &p)
+{
+    float fd = (float)d;
+    if (d > 0) return -(fd * p.delta) / p.eta_c;
+    if (d < 0) return -(fd * p.delta) * p.eta_d;
+    return 0.0f;
+}
+
+__device__ __forceinline__ float move_reward(float lam, int d, const Payoff &p)
+{
+    float g = move_energy(d, p);
+    float r = lam * g - p.c_deg * fabsf(g);
+    return d != 0 ? r - p.c_start : r;
+}
+
+// ------------------------------------------------------------------------------------
+// Expectation C = A * B on MFMA (v_mfma_f32_16x16x4_f32, FP32 products and accumulation).
+// A is K x K (P_t, or its transpose), B is K x N with leading dimension ldb, C is K x N.
+// One wave computes one 16 x 16 tile of C; the reduction over K runs in chunks of
+// CH = 32 MFMA steps (128 terms) whose operands are all loaded before the chunk's
+// MFMA chain starts, so a chunk costs one memory round trip, not one per step.
+// Lane layout of the 16x16x4 instruction: A[i][kk] from lane i + 16 kk, B[kk][j] from
+// lane j + 16 kk, result row 4 (lane / 16) + v, column lane % 16 in register v.
+// ------------------------------------------------------------------------------------
+template <bool TRANS_A>
+__global__ __launch_bounds__(256) void contract_kernel(const float *__restrict__ A,
+                                                       const float *__restrict__ B, int ldb,
+                                                       float *__restrict__ C, int ldc, int K,
+                                                       int N)
+{
+    constexpr int CH = 32;
+    const int ntm = (K + 15) >> 4;
+    const int ntn = (N + 15) >> 4;
+    const int wid = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wid >= ntm * ntn) return;
+    const int tm = wid % ntm, tn = wid / ntm;
+    const int lane = threadIdx.x & 63;
+    const int arow = tm * 16 + (lane & 15);
+    const int kq = lane >> 4;
+    const int col = tn * 16 + (lane & 15);
+    const bool rok = arow < K, cok = col < N;
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 4 * CH) {
+        float av[CH], bv[CH];
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+            const int kx = k0 + 4 * i + kq;
+            const bool kok = kx < K;
+            av[i] = (kok && rok) ? (TRANS_A ? A[(size_t)kx * K + arow] : A[(size_t)arow * K + kx]) : 0.f;
+            bv[i] = (kok && cok) ? B[(size_t)kx * ldb + col] : 0.f;
+        }
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+            if (k0 + 4 * i < K) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[i], acc, 0, 0, 0);
+        }
+    }
+    if (cok) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = tm * 16 + 4 * kq + v;
+            if (r < K) C[(size_t)r * ldc + col] = acc[v];
+        }
+    }
+}
+
+hipError_t launch_contract(const float *A, bool transA, const float *B, int ldb, float *C,
+                           int ldc, int K, int N, hipStream_t stream)
+{
+    const int tiles = ((K + 15) / 16) * ((N + 15) / 16);
+    const int blocks = (tiles + 3) / 4;
+    if (transA)
+        hipLaunchKernelGGL(contract_kernel<true>, dim3(blocks), dim3(256), 0, stream, A, B, ldb, C,
+                           ldc, K, N);
+    else
+        hipLaunchKernelGGL(contract_kernel<false>, dim3(blocks), dim3(256), 0, stream, A, B, ldb,
+                           C, ldc, K, N);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------
+// Max-plus Bellman sweep with argmax (Algorithm 1: gather, -inf mask, payoff, max).
+//
+// Block = one price state k and a tile of TS consecutive SoC indices.  The expectation
+// row W_t[k][.] for every next state the tile can reach is staged in LDS with -inf
+// outside [0, S) (the infeasibility mask), together with the reward row r(lam, d) for the
+// tile's move range (-inf past its end).  Each lane owns R consecutive outputs; the move
+// range is cut into chunks of D moves and the chunks are split over NSPLIT waves.
+//
+// Inner loop: per output and chunk, the running maximum absorbs D candidates
+// (an add and a max each; pairs of maxima fold into v_max3), and the index of the
+// first chunk that raised the maximum is kept.  After the waves' partial results are
+// merged (lowest move range first, strict >), the winning chunk is scanned once more
+// to find the first move whose candidate equals the maximum: candidates are recomputed
+// from the same operands, so the equality is exact, and "first chunk, then first move
+// within it" is the smallest next state attaining the maximum.
+// ------------------------------------------------------------------------------------
+template <int R, int D, int NW, int NSPLIT>
+__global__ __launch_bounds__(NW * 64) void sweep_kernel(SweepArgs a)
+{
+    constexpr int NS = NW / NSPLIT;
+    constexpr int TS = 64 * R * NS;
+    extern __shared__ float4 smem4[];
+    float *smem = reinterpret_cast<float *>(smem4);
+
+    const int k = blockIdx.y;
+    const int s0 = blockIdx.x * TS;
+    const int S = a.S;
+    const int s_end = min(s0 + TS, S);
+    const int dlo = max(-a.w_down, -(s_end - 1));
+    const int dhi = min(a.w_up, S - 1 - s0);
+    const int span = dhi - dlo + 1;
+    const int nchunk = (span + D - 1) / D;
+    const int nrl = nchunk * D;
+    const int nwl = (TS + nrl + R + 3) & ~3;
+    float *Wl = smem;
+    float *rl = smem + nwl;
+    float *pb = rl + nrl;
+    int *pc = reinterpret_cast<int *>(pb + NSPLIT * TS);
+
+    const int tid = threadIdx.x;
+    const float lam = a.lam[k];
+    const float NEG = -INFINITY;
+    for (int i = tid; i < nrl; i += NW * 64) {
+        const int d = dlo + i;
+        rl[i] = (d <= dhi) ? move_reward(lam, d, a.pay) : NEG;
+    }
+    const float *Wk = a.W + (size_t)k * a.ldw;
+    for (int i = tid; i < nwl; i += NW * 64) {
+        const int j = s0 + dlo + i;
+        Wl[i] = (j >= 0 && j < S) ? Wk[j] : NEG;
+    }
+    __syncthreads();
+
+    const int wave = tid >> 6, lane = tid & 63;
+    const int ws = wave % NS, wsp = wave / NS;
+    const int c_begin = (wsp * nchunk) / NSPLIT;
+    const int c_end = ((wsp + 1) * nchunk) / NSPLIT;
+    const int base = (ws * 64 + lane) * R;
+
+    float best[R];
+    int cid[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        best[i] = NEG;
+        cid[i] = -1;
+    }
+    for (int c = c_begin; c < c_end; ++c) {
+        float w[R + D];
+        const float4 *src = reinterpret_cast<const float4 *>(Wl + base + c * D);
+#pragma unroll
+        for (int m = 0; m < (R + D) / 4; ++m) {
+            const float4 v = src[m];
+            w[4 * m + 0] = v.x;
+            w[4 * m + 1] = v.y;
+            w[4 * m + 2] = v.z;
+            w[4 * m + 3] = v.w;
+        }
+        float r[D];
+        const float4 *rsrc = reinterpret_cast<const float4 *>(rl + c * D);
+#pragma unroll
+        for (int m = 0; m < D / 4; ++m) {
+            const float4 v = rsrc[m];
+            r[4 * m + 0] = v.x;
+            r[4 * m + 1] = v.y;
+            r[4 * m + 2] = v.z;
+            r[4 * m + 3] = v.w;
+        }
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            float m = best[i];
+#pragma unroll
+            for (int d = 0; d < D; ++d) m = fmaxf(m, w[i + d] + r[d]);
+            cid[i] = (m > best[i]) ? c : cid[i];
+            best[i] = m;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        pb[wsp * TS + base + i] = best[i];
+        pc[wsp * TS + base + i] = cid[i];
+    }
+    __syncthreads();
+
+    const float shift = a.vprev[0];
+    const double Ct = a.off_next[0] + (double)shift;
+    for (int o = tid; o < TS; o += NW * 64) {
+        const int s = s0 + o;
+        if (s >= S) break;
+        float bv = NEG;
+        int bc = 0;
+#pragma unroll
+        for (int p = 0; p < NSPLIT; ++p) {
+            const float v = pb[p * TS + o];
+            if (v > bv) {
+                bv = v;
+                bc = pc[p * TS + o];
+            }
+        }
+        int arg = 0;
+#pragma unroll
+        for (int d = D - 1; d >= 0; --d) {
+            const float x = Wl[o + bc * D + d] + rl[bc * D + d];
+            if (x == bv) arg = d;
+        }
+        const int j = s + dlo + bc * D + arg;
+        const float vn = bv - shift;
+        const size_t idx = (size_t)k * S + s;
+        a.vnorm[(size_t)k * a.ldv + s] = vn;
+        if (a.vabs) a.vabs[idx] = (float)((double)vn + Ct);
+        if (a.pol) a.pol[idx] = (int16_t)j;
+        if (a.ckpt_v) a.ckpt_v[idx] = vn;
+    }
+    if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) {
+        a.off_cur[0] = Ct;
+        if (a.ckpt_off) a.ckpt_off[0] = Ct;
+    }
+}
+
+int sweep_tile(const SweepShape &sh) { return 64 * sh.R * (sh.NW / sh.NSPLIT); }
+
+size_t sweep_lds_bytes(const SweepShape &sh, int w_up, int w_down)
+{
+    const int TS = sweep_tile(sh);
+    const int span = w_up + w_down + 1;
+    const int nrl = ((span + sh.D - 1) / sh.D) * sh.D;
+    const int nwl = (TS + nrl + sh.R + 3) & ~3;
+    return sizeof(float) * ((size_t)nwl + nrl + (size_t)sh.NSPLIT * TS) +
+           sizeof(int) * (size_t)sh.NSPLIT * TS;
+}
+
+#define DP_SWEEP_SHAPES(X) \
+    X(8, 16, 4, 4)         \
+    X(8, 16, 8, 8)         \
+    X(4, 16, 8, 8)         \
+    X(4, 16, 4, 4)         \
+    X(8, 8, 4, 4)          \
+    X(4, 8, 4, 2)          \
+    X(8, 16, 4, 2)         \
+    X(4, 16, 8, 4)
+
+bool sweep_shape_supported(const SweepShape &sh)
+{
+#define X(r, d, nw, ns) \
+    if (sh.R == r && sh.D == d && sh.NW == nw && sh.NSPLIT == ns) return true;
+    DP_SWEEP_SHAPES(X)
+#undef X
+    return false;
+}
+
+hipError_t launch_sweep(const SweepArgs &a, const SweepShape &sh, hipStream_t stream)
+{
+    const int TS = sweep_tile(sh);
+    dim3 grid((a.S + TS - 1) / TS, a.K);
+    const size_t lds = sweep_lds_bytes(sh, a.w_up, a.w_down);
+#define X(r, d, nw, ns)                                                                  \
+    if (sh.R == r && sh.D == d && sh.NW == nw && sh.NSPLIT == ns) {                      \
+        hipLaunchKernelGGL((sweep_kernel<r, d, nw, ns>), grid, dim3(nw * 64), lds, stream, \
+                           a);                                                           \
+        return hipGetLastError();                                                        \
+    }
+    DP_SWEEP_SHAPES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------------------------------
+// Terminal state: normalised values = src (v_term, a checkpoint, or 0) with offset
+// *src_off (or 0); optional absolute copy (float)(value + offset).
+// ------------------------------------------------------------------------------------
+__global__ void init_terminal_kernel(const float *src, const double *src_off, int K, int S,
+                                     float *vnorm, int ldv, double *off, float *vabs)
+{
+    const double o = src_off ? src_off[0] : 0.0;
+    const size_t n = (size_t)K * S;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const int k = (int)(i / S), s = (int)(i % S);
+        const float v = src ? src[i] : 0.0f;
+        vnorm[(size_t)k * ldv + s] = v;
+        if (vabs) vabs[i] = (float)((double)v + o);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) off[0] = o;
+}
+
+hipError_t launch_init_terminal(const float *src, const double *src_off, int K, int S,
+                                float *vnorm, int ldv, double *off, float *vabs,
+                                hipStream_t stream)
+{
+    const size_t n = (size_t)K * S;
+    int blocks = (int)((n + 255) / 256);
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(init_terminal_kernel, dim3(blocks), dim3(256), 0, stream, src, src_off,
+                       K, S, vnorm, ldv, off, vabs);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------
+// Adjoint: push the occupation measure through the policy (deterministic).
+// Block = one price state k, 4 waves; wave w owns a contiguous quarter of the SoC range
+// and its own LDS accumulator nu_w[S].  Each 64-lane chunk is bitonic-sorted by
+// (next state j, lane), a segmented scan sums the masses of equal j in lane order, and
+// the last lane of every segment adds the segment sum into nu_w[j] (one writer per j
+// per chunk, chunks in ascending s).  Finally nu = nu_0 + nu_1 + nu_2 + nu_3 in that
+// order.  grad_lam[k] = sum_s mu[s] g(pi(s) - s), per-lane then a fixed-order tree.
+// ------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void pushforward_kernel(const float *__restrict__ mu,
+                                                          int ldm,
+                                                          const int16_t *__restrict__ pol,
+                                                          int K, int S, Payoff pay,
+                                                          float *__restrict__ nu, int ldn,
+                                                          float *__restrict__ grad_lam)
+{
+    extern __shared__ float4 smem4[];
+    float *acc = reinterpret_cast<float *>(smem4);      // [4][S]
+    __shared__ float red[256];
+    const int k = blockIdx.x;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    for (int i = tid; i < 4 * S; i += 256) acc[i] = 0.0f;
+    __syncthreads();
+    const int q = (((S + 3) / 4) + 63) & ~63;
+    const int sb = wave * q, se = min(S, sb + q);
+    float *my = acc + wave * S;
+    float gl = 0.0f;
+    for (int c = sb; c < se; c += 64) {
+        const int s = c + lane;
+        const bool valid = s < se;
+        const int j = valid ? (int)pol[(size_t)k * S + s] : 0x7fff;
+        const float m = valid ? mu[(size_t)k * ldm + s] : 0.0f;
+        if (valid) gl += m * move_energy(j - s, pay);
+        unsigned key = ((unsigned)j << 6) | (unsigned)lane;
+        float val = m;
+#pragma unroll
+        for (int kk = 2; kk <= 64; kk <<= 1) {
+#pragma unroll
+            for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+                const unsigned okey = __shfl_xor(key, jj);
+                const float oval = __shfl_xor(val, jj);
+                const bool up = (lane & kk) == 0;
+                const bool lower = (lane & jj) == 0;
+                const bool take_min = (lower == up);
+                const bool other_smaller = okey < key;
+                const bool take_other = take_min ? other_smaller : !other_smaller;
+                if (take_other) {
+                    key = okey;
+                    val = oval;
+                }
+            }
+        }
+        const int myj = (int)(key >> 6);
+        float v = val;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const float pv = __shfl_up(v, off);
+            const int pj = __shfl_up(myj, off);
+            if (lane >= off && pj == myj) v += pv;
+        }
+        const int nj = __shfl_down(myj, 1);
+        const bool last = (lane == 63) || (nj != myj);
+        if (last && myj != 0x7fff) my[myj] += v;
+    }
+    red[tid] = gl;
+    __syncthreads();
+    for (int i = tid; i < S; i += 256)
+        nu[(size_t)k * ldn + i] = ((acc[i] + acc[S + i]) + acc[2 * S + i]) + acc[3 * S + i];
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) red[tid] += red[tid + w];
+        __syncthreads();
+    }
+    if (tid == 0) grad_lam[k] = red[0];
+}
+
+hipError_t launch_pushforward(const float *mu, int ldm, const int16_t *pol, int K, int S,
+                              Payoff pay, float *nu, int ldn, float *grad_lam,
+                              hipStream_t stream)
+{
+    const size_t lds = sizeof(float) * 4 * (size_t)S;
+    hipLaunchKernelGGL(pushforward_kernel, dim3(K), dim3(256), lds, stream, mu, ldm, pol, K,
+                       S, pay, nu, ldn, grad_lam);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------
+// grad_P_t = nu_t V_{t+1}^T on MFMA: gP[k][k'] = sum_j nu[k][j] V[k'][j].
+// Block = one 16 x 16 output tile, 4 waves each reducing a contiguous quarter of j;
+// the four partial tiles are added in wave order.
+// ------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void gradP_kernel(const float *__restrict__ nu, int ldn,
+                                                    const float *__restrict__ V, int K, int S,
+                                                    float *__restrict__ gP)
+{
+    __shared__ float part[4][256];
+    const int ntm = (K + 15) >> 4;
+    const int tm = blockIdx.x % ntm, tn = blockIdx.x / ntm;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int kq = lane >> 4;
+    const int arow = tm * 16 + (lane & 15);   // k
+    const int bcol = tn * 16 + (lane & 15);   // k'
+    const int steps = (S + 3) / 4;
+    const int per = (steps + 3) / 4;
+    const int jb = wave * per * 4, je = min(S, (wave + 1) * per * 4);
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int j0 = jb; j0 < je; j0 += 4) {
+        const int j = j0 + kq;
+        float av = 0.f, bv = 0.f;
+        if (j < je) {
+            if (arow < K) av = nu[(size_t)arow * ldn + j];
+            if (bcol < K) bv = V[(size_t)bcol * S + j];
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) part[wave][(4 * kq + v) * 16 + (lane & 15)] = acc[v];
+    __syncthreads();
+    const int r = tid >> 4, c = tid & 15;
+    const int kr = tm * 16 + r, kc = tn * 16 + c;
+    if (kr < K && kc < K)
+        gP[(size_t)kr * K + kc] = ((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid];
+}
+
+hipError_t launch_gradP(const float *nu, int ldn, const float *V, int K, int S, float *gP,
+                        hipStream_t stream)
+{
+    const int nt = (K + 15) / 16;
+    hipLaunchKernelGGL(gradP_kernel, dim3(nt * nt), dim3(256), 0, stream, nu, ldn, V, K, S, gP);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------
+// Small utilities.
+// ------------------------------------------------------------------------------------
+__global__ void copy_rows_kernel(const float *src, int lds, float *dst, int ldd, int K, int S)
+{
+    const size_t n = (size_t)K * S;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const int k = (int)(i / S), s = (int)(i % S);
+        dst[(size_t)k * ldd + s] = src[(size_t)k * lds + s];
+    }
+}
+
+hipError_t launch_copy_rows(const float *src, int lds, float *dst, int ldd, int K, int S,
+                            hipStream_t stream)
+{
+    const size_t n = (size_t)K * S;
+    int blocks = (int)((n + 255) / 256);
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(copy_rows_kernel, dim3(blocks), dim3(256), 0, stream, src, lds, dst, ldd,
+                       K, S);
+    return hipGetLastError();
+}
+
+__global__ void fill_kernel(float *dst, size_t n, float v)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = v;
+}
+
+hipError_t launch_fill(float *dst, size_t n, float v, hipStream_t stream)
+{
+    int blocks = (int)((n + 255) / 256);
+    if (blocks > 2048) blocks = 2048;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(fill_kernel, dim3(blocks), dim3(256), 0, stream, dst, n, v);
+    return hipGetLastError();
+}
+
+// Row check of the transition tensor: every entry >= 0 and |row sum - 1| <= 1e-6.
+__global__ void validate_P_kernel(const float *P, int T, int K, int *flag)
+{
+    const size_t rows = (size_t)T * K;
+    for (size_t r = blockIdx.x * (size_t)blockDim.x + threadIdx.x; r < rows;
+         r += (size_t)gridDim.x * blockDim.x) {
+        double sum = 0.0;
+        bool neg = false;
+        for (int c = 0; c < K; ++c) {
+            const float v = P[r * K + c];
+            neg |= !(v >= 0.0f);
+            sum += (double)v;
+        }
+        if (neg || fabs(sum - 1.0) > 1e-6) atomicOr(flag, 1);
+    }
+}
+
+hipError_t launch_validate_P(const float *P, int T, int K, int *flag, hipStream_t stream)
+{
+    const size_t rows = (size_t)T * K;
+    int blocks = (int)((rows + 255) / 256);
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(validate_P_kernel, dim3(blocks), dim3(256), 0, stream, P, T, K, flag);
+    return hipGetLastError();
+}
+
+}  // namespace dpk

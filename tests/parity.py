@@ -1,0 +1,86 @@
+"""Comparison rules between the HIP path and the FP64 oracle (shared by the GPU tests).
+
+Values: per stage, max_{k,s} |V_gpu - V_or| <= RTOL * max_{k,s} |V_or| (normwise; an
+elementwise relative test is meaningless where V crosses 0).  RTOL = 1e-5.
+
+Policies: identical, except at near-ties: a mismatch at (t, k, s) is accepted iff the
+oracle's own Q value of the GPU's choice is within RTOL * max|V_or,t| of the oracle's
+maximum (FP32 and FP64 may order two candidates that close differently).  Every
+accepted mismatch is counted and reported.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+
+RTOL = 1e-5
+
+
+def value_error(v_gpu: np.ndarray, v_or: np.ndarray) -> float:
+    scale = max(float(np.max(np.abs(v_or))), 1e-30)
+    return float(np.max(np.abs(v_gpu.astype(np.float64) - v_or))) / scale
+
+
+def check_stage(st, lam_t, P_t, v_next_or, v_gpu, pol_gpu, *, v_or=None, pol_or=None,
+                label=""):
+    """Compare one stage's GPU values and policies against the oracle.
+
+    v_next_or is the FP64 V_{t+1} the oracle uses; v_or/pol_or may be passed if
+    already computed.  Returns the number of accepted near-tie policy mismatches.
+    """
+    W = None
+    if v_or is None or pol_or is None:
+        v_or, pol_or, W = oracle.stage(st, lam_t, P_t, v_next_or, want_w=True)
+    err = value_error(v_gpu, v_or)
+    assert err <= RTOL, f"{label}: normwise value error {err:.3e} > {RTOL}"
+    mism = np.argwhere(pol_gpu != pol_or)
+    if mism.size == 0:
+        return 0
+    if W is None:
+        _, _, W = oracle.stage(st, lam_t, P_t, v_next_or, want_w=True)
+    tol = RTOL * max(float(np.max(np.abs(v_or))), 1e-30)
+    for k, s in mism:
+        q = oracle.q_values(st, float(lam_t[k]), W[k], int(s))
+        j = int(pol_gpu[k, s])
+        assert np.isfinite(q[j]), f"{label}: GPU chose infeasible j={j} at k={k}, s={s}"
+        assert q[j] >= v_or[k, s] - tol, (
+            f"{label}: policy mismatch at k={k} s={s}: gpu j={j} (Q={q[j]:.9g}) vs "
+            f"oracle j={int(pol_or[k, s])} (V={v_or[k, s]:.9g})")
+        STATS["max_regret"] = max(STATS["max_regret"], float(v_or[k, s] - q[j]) / scale)
+    return int(mism.shape[0])
+
+
+def check_solve(st, lam, P, V_gpu_all, pol_gpu, or_out, label=""):
+    """Full-solve comparison, stage by stage; returns total accepted mismatches."""
+    T = lam.shape[0]
+    V_or = or_out["V"]
+    pol_or = or_out["policy"]
+    total = 0
+    for t in range(T, 0, -1):
+        err = value_error(V_gpu_all[t - 1], V_or[t - 1])
+        assert err <= RTOL, f"{label} stage {t}: normwise value error {err:.3e}"
+        if not np.array_equal(pol_gpu[t - 1], pol_or[t - 1]):
+            total += _mismatch(st, lam[t - 1], P[t - 1], V_or[t], V_or[t - 1], pol_gpu[t - 1],
+                               pol_or[t - 1], f"{label} stage {t}")
+    return total
+
+
+STATS = {"mismatch": 0, "max_regret": 0.0}
+
+
+def _mismatch(st, lam_t, P_t, v_next_or, v_or, pol_gpu, pol_or, label):
+    _, _, W = oracle.stage(st, lam_t, P_t, v_next_or, want_w=True)
+    scale = max(float(np.max(np.abs(v_or))), 1e-30)
+    tol = RTOL * scale
+    mism = np.argwhere(pol_gpu != pol_or)
+    STATS["mismatch"] += int(mism.shape[0])
+    for k, s in mism:
+        q = oracle.q_values(st, float(lam_t[k]), W[k], int(s))
+        j = int(pol_gpu[k, s])
+        assert np.isfinite(q[j]), f"{label}: GPU chose infeasible j={j} at k={k}, s={s}"
+        assert q[j] >= v_or[k, s] - tol, (
+            f"{label}: policy mismatch at k={k} s={s}: gpu j={j} (Q={q[j]:.9g}) vs "
+            f"oracle j={int(pol_or[k, s])} (V={v_or[k, s]:.9g})")
+        STATS["max_regret"] = max(STATS["max_regret"], float(v_or[k, s] - q[j]) / scale)
+    return int(mism.shape[0])

@@ -1,0 +1,153 @@
+"""GPU parity of the backward induction (dp_solve through the C ABI) against the oracle."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from parity import RTOL, check_solve, check_stage, value_error
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2511_15629_amd as m
+    return m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def gpu_solve(dp, inst, v_term=None, **kw):
+    out = dp.solve(dev(inst.lam), dev(inst.P), inst.storage,
+                   None if v_term is None else dev(v_term.astype(np.float32)), **kw)
+    torch.cuda.synchronize()
+    return out
+
+
+def full_parity(dp, inst, v_term=None, threads=0):
+    out = gpu_solve(dp, inst, v_term, store_all=True)
+    V = out["V"].cpu().numpy()
+    pol = out["policy"].cpu().numpy()
+    ref = oracle.solve(inst.storage, inst.lam, inst.P,
+                       None if v_term is None else v_term.astype(np.float32).astype(np.float64),
+                       threads=threads)
+    n = check_solve(inst.storage, inst.lam, inst.P, V, pol, ref, label=inst.name)
+    return n, V, pol, ref
+
+
+RAGGED = [
+    dict(seed=1, T=5, K=3, S=7, wu=2, wd=3, c_start=1.0),
+    dict(seed=2, T=6, K=17, S=600, wu=40, wd=70),
+    dict(seed=3, T=4, K=33, S=1300, wu=300, wd=5, c_start=2.5),
+    dict(seed=4, T=3, K=1, S=2, wu=1, wd=1),
+    dict(seed=5, T=4, K=5, S=40, wu=0, wd=0),
+    dict(seed=6, T=3, K=4, S=257, wu=256, wd=256, lam_lo=-150.0),
+    dict(seed=7, T=5, K=64, S=512, wu=64, wd=64, c_deg=0.0),
+    dict(seed=8, T=4, K=20, S=2001, wu=160, wd=190, eta=0.86),
+    dict(seed=9, T=7, K=2, S=129, wu=1, wd=100),
+]
+
+
+@pytest.mark.parametrize("case", RAGGED, ids=lambda c: f"s{c['seed']}_K{c['K']}_S{c['S']}")
+def test_ragged_shapes_match_oracle(dp, case):
+    kw = dict(case)
+    seed, T, K, S, wu, wd = (kw.pop(k) for k in ("seed", "T", "K", "S", "wu", "wd"))
+    inst = wl.random_small(seed, T, K, S, wu, wd, **kw)
+    v_term = None
+    if seed % 3 == 0:
+        v_term = np.random.default_rng(seed).uniform(-20, 20, size=(K, S))
+    n, V, pol, ref = full_parity(dp, inst, v_term)
+    print(f"{inst.name}: accepted near-tie policy mismatches = {n}")
+
+
+def test_hourly_day_small_matches_oracle(dp):
+    inst = wl.day_hourly_small()
+    n, V, pol, ref = full_parity(dp, inst)
+    assert n <= 0.001 * pol.size
+
+
+def test_five_minute_day_full_size_matches_oracle(dp):
+    inst = wl.day_5min()
+    n, V, pol, ref = full_parity(dp, inst)
+    print(f"{inst.name}: accepted near-tie mismatches {n} of {pol.size}")
+    # every mismatch already passed the near-tie rule; a systematic error would show as
+    # far more of them
+    assert n <= 0.01 * pol.size
+
+
+def test_year_shapes_one_week_matches_oracle(dp):
+    inst = wl.year_hourly(T=168)
+    n, V, pol, ref = full_parity(dp, inst)
+    print(f"{inst.name}: accepted near-tie mismatches {n} of {pol.size}")
+    assert n <= 0.01 * pol.size
+
+
+def test_year_full_size_sampled_stages(dp):
+    """T = 8760: each sampled stage t is recomputed by the oracle from the GPU's V_{t+1}."""
+    inst = wl.year_hourly()
+    out = gpu_solve(dp, inst, store_all=True)
+    Vd, pold = out["V"], out["policy"]
+    T = inst.T
+    for t in (T, T - 1, 6000, 4380, 1234, 2, 1):
+        v_next = Vd[t].cpu().numpy().astype(np.float64)
+        v_gpu = Vd[t - 1].cpu().numpy()
+        p_gpu = pold[t - 1].cpu().numpy()
+        check_stage(inst.storage, inst.lam[t - 1], inst.P[t - 1], v_next, v_gpu, p_gpu,
+                    label=f"year stage {t}")
+    assert np.all(np.isfinite(Vd[0].cpu().numpy()))
+    del out, Vd, pold
+    torch.cuda.empty_cache()
+
+
+def test_v1_only_equals_all_stage_slice_bitwise(dp):
+    inst = wl.random_small(21, 9, 12, 300, 30, 20, c_start=1.0)
+    a = gpu_solve(dp, inst, store_all=True)
+    b = gpu_solve(dp, inst, store_all=False, policy=False)
+    assert torch.equal(a["V"][0], b["V"])
+
+
+def test_repeat_runs_are_bitwise_identical(dp):
+    inst = wl.day_hourly_small()
+    a = gpu_solve(dp, inst, store_all=True)
+    b = gpu_solve(dp, inst, store_all=True)
+    assert torch.equal(a["V"], b["V"]) and torch.equal(a["policy"], b["policy"])
+
+
+@pytest.mark.parametrize("shape", [(8, 16, 4, 4), (4, 16, 8, 8), (8, 8, 4, 4), (4, 8, 4, 2),
+                                   (8, 16, 4, 2), (4, 16, 8, 4)])
+def test_tile_shapes_give_bitwise_identical_results(dp, shape):
+    inst = wl.random_small(31, 6, 21, 1100, 260, 180, c_start=3.0, lam_lo=-60.0)
+    dp.set_sweep_shape()
+    ref = gpu_solve(dp, inst, store_all=True)
+    try:
+        dp.set_sweep_shape(*shape)
+        got = gpu_solve(dp, inst, store_all=True)
+    finally:
+        dp.set_sweep_shape()
+    assert torch.equal(ref["V"], got["V"]) and torch.equal(ref["policy"], got["policy"])
+
+
+def test_checkpoint_buffer_does_not_change_results(dp):
+    inst = wl.random_small(41, 40, 6, 200, 20, 20)
+    a = gpu_solve(dp, inst, store_all=True)
+    b = gpu_solve(dp, inst, store_all=True, ckpt_every=7)
+    assert torch.equal(a["V"], b["V"]) and torch.equal(a["policy"], b["policy"])
+
+
+def test_validation_rejects_non_stochastic_rows(dp):
+    inst = wl.random_small(51, 3, 4, 10, 2, 2)
+    P = inst.P.copy()
+    P[1, 2, 0] += np.float32(0.01)
+    with pytest.raises(dp.DPError) as e:
+        dp.solve(dev(inst.lam), dev(P), inst.storage, validate=True)
+    assert e.value.code == -2
+    dp.solve(dev(inst.lam), dev(inst.P), inst.storage, validate=True)
+    torch.cuda.synchronize()
