@@ -10,8 +10,9 @@ int16 policies to HBM.  The metric is feasible state-action updates per second (
 HBM before the timed region.  One JSON line is printed; besides the required fields it
 carries:
   roofline      the Bellman-sweep kernel (dominant): feasible candidates per launch over
-                its average launch time measured with HIP events on the solve's stream
-                during the timed steps, against the VALU issue bound (see DESIGN.md);
+                its average launch time, measured with HIP events on the solve's stream
+                in a second pass of the same steps right after the timed ones, against
+                the VALU issue bound (1.5 lane-instructions per candidate);
   cpu_baseline  the FP64 oracle timed on this host's cores on a bounded sample;
   extra         the year-long hourly solve, the adjoint/value time ratio and the
                 batched/looped comparison, each on the same GPU.
@@ -37,25 +38,28 @@ def host_cores() -> int:
         return os.cpu_count() or 1
 
 
-def timed_solves(dp, torch, inst, steps, warmup, events=True):
+def timed_solves(dp, torch, inst, steps, warmup):
+    """Wall time per step over `steps` solves (no instrumentation), then the same number
+    of identical solves with HIP event pairs (created without the system-scope fence) on
+    the solve's stream around every sweep and expectation launch; event packets between
+    launches slow the steps down, so they are kept out of the timed steps."""
     lam = torch.from_numpy(inst.lam).cuda()
     P = torch.from_numpy(inst.P).cuda()
     solver = dp.Solver(lam, P, inst.storage, store_all=False, policy=True)
     for _ in range(warmup):
         solver.run()
     torch.cuda.synchronize()
-    if events:
-        dp.kernel_timing(True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         solver.run()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    timing = None
-    if events:
-        timing = dp.kernel_timing()
-        dp.kernel_timing(False)
+    dp.lib().dp_set_timing(2)
+    for _ in range(steps):
+        solver.run()
+    torch.cuda.synchronize()
+    timing = dp.kernel_timing()
+    dp.kernel_timing(False)
     del solver
     return (t1 - t0) / steps, timing
 
@@ -129,10 +133,11 @@ def adjoint_ratio(dp, torch, inst, reps=5):
 def batch_compare(dp, torch, reps=2):
     import workloads as wl
     insts = wl.fleet_5min()
-    try:
-        plan = dp.BatchPlan([(i.T, i.K, i.storage) for i in insts])
-    except dp.DPError as e:
-        return {"skipped": str(e)}
+    import tempfile
+    cache_path = os.path.join(tempfile.gettempdir(), "dpgpu_tune_cache.txt")
+    t0 = time.perf_counter()
+    plan = dp.BatchPlan([(i.T, i.K, i.storage) for i in insts], tune_cache=cache_path)
+    plan_s = time.perf_counter() - t0
     cache = {}
     lams, Ps, V1s, pols = [], [], [], []
     for i in insts:
@@ -144,7 +149,8 @@ def batch_compare(dp, torch, reps=2):
         V1s.append(torch.empty(i.K, i.storage.S, device="cuda"))
         pols.append(torch.empty(i.T, i.K, i.storage.S, dtype=torch.int16, device="cuda"))
     cand = sum(i.candidates() for i in insts)
-    out = {"instances": len(insts), "candidates": cand}
+    out = {"instances": len(insts), "candidates": cand, "plan_create_s": round(plan_s, 2),
+           "plan": plan.describe().strip().splitlines()}
     for looped in (False, True):
         plan.solve(lams, Ps, V1s, pols, looped=looped)
         torch.cuda.synchronize()
@@ -170,8 +176,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build solves on one GPU only (asked for {args.gpus}); the "
-              "multi-GPU sharding of the batched solve is described in DESIGN.md",
+        print(f"bench.py: the solver runs on a single GPU (asked for {args.gpus}); batches "
+              "shard across GPUs by instance, which this benchmark does not run",
               file=sys.stderr)
         sys.exit(2)
 

@@ -100,7 +100,8 @@ const char *dp_last_error(void);
  * shape this build has no kernel for.  Not thread-safe with concurrent solves. */
 int dp_set_sweep_shape(int R, int D, int NW, int NSPLIT);
 
-/* Measurement hook: while on, dp_solve records a pair of HIP events on its stream around
+/* Measurement hook: while on (1, or 2 for events created without the system-scope
+ * fence), dp_solve records a pair of HIP events on its stream around
  * every Bellman-sweep launch and every expectation launch.  dp_get_timing waits for the
  * recorded events, returns the summed elapsed milliseconds and launch counts of each
  * kind since the last call (or since dp_set_timing), and resets the record.  Host-side

@@ -1,7 +1,6 @@
 // Host side of libdpgpu: argument validation, workspace layout, the stage loop of the
 // backward induction and the forward-in-time adjoint driver.  See include/dpgpu.h.
-#include "dpgpu.h"
-#include "dp_internal.h"
+#include "dp_host.h"
 
 #include <math.h>
 #include <stdarg.h>
@@ -14,6 +13,10 @@
 namespace {
 
 thread_local std::string g_last_error;
+
+}  // namespace
+
+namespace dpgpu {
 
 int fail(int code, const char *fmt, ...)
 {
@@ -31,12 +34,20 @@ int hip_fail(hipError_t e, const char *what)
     return fail(DP_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
+}  // namespace dpgpu
+
+namespace {
+
+using dpgpu::fail;
+using dpgpu::hip_fail;
+
 dpk::SweepShape g_shape_override = {0, 0, 0, 0};
 
 // Optional per-kernel timing (dp_set_timing): HIP events recorded on the caller's stream
 // around every sweep and expectation launch of dp_solve.
 struct KernelTimer {
     bool on = false;
+    unsigned flags = hipEventDefault;
     std::vector<hipEvent_t> ev;      // pairs (start, stop)
     std::vector<int> kind;           // 0 = sweep, 1 = expectation
     size_t used = 0;
@@ -49,7 +60,7 @@ hipError_t timer_mark(hipStream_t s, int kind, bool start)
         if (g_timer.used + 2 > g_timer.ev.size()) {
             for (int i = 0; i < 256; ++i) {
                 hipEvent_t e;
-                hipError_t r = hipEventCreate(&e);
+                hipError_t r = hipEventCreateWithFlags(&e, g_timer.flags);
                 if (r != hipSuccess) return r;
                 g_timer.ev.push_back(e);
             }
@@ -96,11 +107,6 @@ dpk::SweepShape pick_shape(const dp_problem *pb)
     return dpk::SweepShape{4, 8, 4, 2};
 }
 
-struct SolveLayout {
-    int Spad;
-    size_t vA, vB, W, off, flag, total;
-};
-
 SolveLayout solve_layout(const dp_problem *pb)
 {
     SolveLayout L;
@@ -131,17 +137,8 @@ size_t ckpt_bytes(const dp_problem *pb)
 
 // Backward induction over stages [t_lo, t_hi] (1-based) of the problem.  The terminal
 // state (stage t_hi + 1) is v_src (absolute v_term or a normalised checkpoint) with
-// offset *off_src (device pointer or NULL = 0).  Values at stage t are written to
-// vabs_at(t) if non-null; policies to pol + (t - t_lo) K S.
-struct StageOutputs {
-    float *vall;         // [(t_hi - t_lo + 2)][K][S] absolute values, slice t - t_lo (nullable)
-    float *v1;           // [K][S] absolute values of stage t_lo (nullable)
-    int16_t *pol;        // [(t_hi - t_lo + 1)][K][S] (nullable)
-    float *ckpt_v;       // checkpoint slots (nullable)
-    double *ckpt_off;
-    int ckpt_every;
-};
-
+// offset *off_src (device pointer or NULL = 0).  Absolute values of stage t go to
+// out.vall slice t - t_lo (or out.v1 for t = t_lo), policies to out.pol slice t - t_lo.
 int run_stages(const dp_problem *pb, int t_lo, int t_hi, const float *lam, const float *P,
                const float *v_src, const double *off_src, const StageOutputs &out, void *ws,
                hipStream_t stream)
@@ -256,6 +253,13 @@ int dp_set_sweep_shape(int R, int D, int NW, int NSPLIT)
 
 int dp_set_timing(int on)
 {
+    // 1: default events; 2: events without the system-scope fence (lighter packets)
+    const unsigned flags = on == 2 ? hipEventDisableSystemFence : hipEventDefault;
+    if (flags != g_timer.flags) {
+        for (hipEvent_t e : g_timer.ev) (void)hipEventDestroy(e);
+        g_timer.ev.clear();
+        g_timer.flags = flags;
+    }
     g_timer.on = on != 0;
     g_timer.used = 0;
     g_timer.kind.clear();

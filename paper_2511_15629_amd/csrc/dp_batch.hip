@@ -1,39 +1,472 @@
-// Batched solves (placeholder until the persistent batched kernel lands).
-#include "dpgpu.h"
+// Batched solves of many independent instances.
+//
+// All instances advance together, one batch stage per step: stage tau runs one
+// expectation launch over the contraction tiles of every instance and one sweep launch
+// per tile class over the (instance, price state, SoC tile) blocks of that class.
+// Instance i is at its own stage T_i - tau + 1, so instances of different horizons
+// finish on the same last step.  The whole sequence (an init launch and the per-stage
+// launches) is captured once into a HIP graph and replayed; new input/output pointers
+// are written into the device descriptor table before each replay, so the graph never
+// needs re-capture.
+//
+// Tile classes: instances are grouped by the move span (w_up + w_down + 1); each group
+// gets a sweep tile shape, either the built-in choice or the fastest of the candidate
+// shapes timed on the group's own work list (autotuning), remembered in a text cache.
+// The shape never changes results (every shape is bitwise equal), only speed.
+#include "dp_host.h"
+
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <string>
+#include <vector>
+
+using namespace dpgpu;
+
+namespace {
+
+const dpk::SweepShape kCandidates[] = {
+    {8, 16, 8, 8}, {4, 16, 8, 8}, {8, 16, 4, 4}, {4, 16, 4, 4}, {8, 8, 4, 4}, {4, 8, 4, 2},
+    {4, 16, 8, 4}, {8, 16, 4, 2}, {8, 8, 4, 1},  {4, 8, 4, 1},  {8, 16, 4, 1}, {4, 16, 4, 1},
+};
+
+struct TileClass {
+    dpk::SweepShape sh;
+    int span_lo, span_hi;
+    std::vector<int> inst;
+    std::vector<dpk::SweepItem> items;
+    dpk::SweepItem *d_items = nullptr;
+    size_t lds = 0;
+    double tuned_us = -1.0;
+};
+
+int span_bucket(int span)
+{
+    int b = 0;
+    while ((32 << b) < span && b < 10) ++b;
+    return b;   // spans (16 << b, 32 << b]
+}
+
+bool shape_fits(const dpk::SweepShape &sh, int w_up, int w_down)
+{
+    return dpk::sweep_lds_bytes(sh, w_up, w_down) <= 160 * 1024;
+}
+
+std::string shape_str(const dpk::SweepShape &sh)
+{
+    char b[64];
+    snprintf(b, sizeof b, "%d %d %d %d", sh.R, sh.D, sh.NW, sh.NSPLIT);
+    return b;
+}
+
+}  // namespace
 
 struct dp_batch_plan {
-    int n;
+    int n = 0;
+    int Tmax = 0;
+    std::vector<dp_problem> probs;
+    std::vector<dpk::BatchDesc> hdesc;
+    std::vector<size_t> region;            // per-instance workspace offsets
+    dpk::BatchDesc *ddesc = nullptr;
+    dpk::BatchDesc *hstage = nullptr;      // pinned staging for descriptor updates
+    std::vector<TileClass> classes;
+    dpk::ContractItem *d_citems = nullptr;
+    int n_citems = 0;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t staged = nullptr;
+    bool staged_pending = false;
+    std::string text;
 };
+
+static void destroy_plan(dp_batch_plan *p)
+{
+    if (!p) return;
+    if (p->staged_pending) (void)hipEventSynchronize(p->staged);
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    for (auto &c : p->classes)
+        if (c.d_items) (void)hipFree(c.d_items);
+    if (p->d_citems) (void)hipFree(p->d_citems);
+    if (p->ddesc) (void)hipFree(p->ddesc);
+    if (p->hstage) (void)hipHostFree(p->hstage);
+    if (p->ws) (void)hipFree(p->ws);
+    if (p->staged) (void)hipEventDestroy(p->staged);
+    if (p->cap) (void)hipStreamDestroy(p->cap);
+    delete p;
+}
+
+// Launch one whole batched solve (init + all stages) on `s`.
+static int enqueue_all(dp_batch_plan *p, hipStream_t s)
+{
+    hipError_t e = dpk::launch_batched_init(p->ddesc, p->n, s);
+    if (e != hipSuccess) return hip_fail(e, "batched init");
+    for (int tau = 1; tau <= p->Tmax; ++tau) {
+        e = dpk::launch_batched_contract(p->ddesc, p->d_citems, p->n_citems, tau, s);
+        if (e != hipSuccess) return hip_fail(e, "batched expectation");
+        for (auto &c : p->classes) {
+            if (c.items.empty()) continue;
+            e = dpk::launch_batched_sweep(p->ddesc, c.d_items, (int)c.items.size(), tau, c.sh,
+                                          c.lds, s);
+            if (e != hipSuccess) return hip_fail(e, "batched sweep");
+        }
+    }
+    return DP_OK;
+}
+
+static int build_items(dp_batch_plan *p, TileClass &c)
+{
+    c.items.clear();
+    c.lds = 0;
+    const int TS = dpk::sweep_tile(c.sh);
+    // heavier instances (wider spans, more outputs) first, for a short tail
+    std::vector<int> order = c.inst;
+    std::sort(order.begin(), order.end(), [&](int a, int b) {
+        const auto &x = p->probs[a].st, &y = p->probs[b].st;
+        return (long)(x.w_up + x.w_down) * p->probs[a].K > (long)(y.w_up + y.w_down) * p->probs[b].K;
+    });
+    for (int i : order) {
+        const dp_problem &pb = p->probs[i];
+        const int tiles = (pb.st.S + TS - 1) / TS;
+        for (int k = 0; k < pb.K; ++k)
+            for (int tl = 0; tl < tiles; ++tl) c.items.push_back({i, k, tl});
+        c.lds = std::max(c.lds, dpk::sweep_lds_bytes(c.sh, pb.st.w_up, pb.st.w_down));
+    }
+    if (c.d_items) {
+        (void)hipFree(c.d_items);
+        c.d_items = nullptr;
+    }
+    if (c.items.empty()) return DP_OK;
+    hipError_t e = hipMalloc(&c.d_items, sizeof(dpk::SweepItem) * c.items.size());
+    if (e == hipSuccess)
+        e = hipMemcpy(c.d_items, c.items.data(), sizeof(dpk::SweepItem) * c.items.size(),
+                      hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "batch item table");
+    return DP_OK;
+}
+
+// Time the class's sweep over a few stages with each candidate shape on the plan's own
+// workspace (values are irrelevant to the cost); keep the fastest.
+static int autotune_class(dp_batch_plan *p, TileClass &c, const float *zeros_lam)
+{
+    double best_us = 1e30;
+    dpk::SweepShape best = c.sh;
+    // every descriptor: the plan's workspace, zero prices (a [Tmax][Kmax] zero block), no
+    // inputs or outputs of the caller
+    for (int i = 0; i < p->n; ++i) {
+        p->hstage[i] = p->hdesc[i];
+        p->hstage[i].lam = zeros_lam;
+        p->hstage[i].P = nullptr;
+        p->hstage[i].pol = nullptr;
+        p->hstage[i].V1 = nullptr;
+    }
+    hipError_t e = hipMemcpy(p->ddesc, p->hstage, sizeof(dpk::BatchDesc) * p->n, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "tune descriptors");
+    e = dpk::launch_batched_init(p->ddesc, p->n, p->cap);
+    if (e != hipSuccess) return hip_fail(e, "tune init");
+    hipEvent_t e0, e1;
+    if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(e, "tune event");
+    if ((e = hipEventCreate(&e1)) != hipSuccess) return hip_fail(e, "tune event");
+    int rc = DP_OK;
+    for (const auto &cand : kCandidates) {
+        bool fits = true;
+        for (int i : c.inst) fits &= shape_fits(cand, p->probs[i].st.w_up, p->probs[i].st.w_down);
+        if (!fits) continue;
+        TileClass trial;
+        trial.sh = cand;
+        trial.inst = c.inst;
+        if ((rc = build_items(p, trial)) != DP_OK) break;
+        // tau = 1 keeps every instance active (stage T_i); the W buffer holds zeros
+        double t_min = 1e30;
+        for (int rep = 0; rep < 4 && rc == DP_OK; ++rep) {
+            e = hipEventRecord(e0, p->cap);
+            for (int st = 0; st < 3 && e == hipSuccess; ++st)
+                e = dpk::launch_batched_sweep(p->ddesc, trial.d_items, (int)trial.items.size(), 1,
+                                              trial.sh, trial.lds, p->cap);
+            if (e == hipSuccess) e = hipEventRecord(e1, p->cap);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) rc = hip_fail(e, "tune timing");
+            if (rep > 0) t_min = std::min(t_min, ms * 1e3 / 3.0);
+        }
+        if (trial.d_items) (void)hipFree(trial.d_items);
+        if (rc != DP_OK) break;
+        if (t_min < best_us) {
+            best_us = t_min;
+            best = cand;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != DP_OK) return rc;
+    c.sh = best;
+    c.tuned_us = best_us;
+    return DP_OK;
+}
+
+static std::map<int, dpk::SweepShape> read_cache(const char *path)
+{
+    std::map<int, dpk::SweepShape> m;
+    if (!path) return m;
+    FILE *f = fopen(path, "r");
+    if (!f) return m;
+    char line[256];
+    while (fgets(line, sizeof line, f)) {
+        if (line[0] == '#') continue;
+        int b, r, d, nw, ns;
+        if (sscanf(line, "%d %d %d %d %d", &b, &r, &d, &nw, &ns) == 5) {
+            dpk::SweepShape sh = {r, d, nw, ns};
+            if (dpk::sweep_shape_supported(sh)) m[b] = sh;
+        }
+    }
+    fclose(f);
+    return m;
+}
+
+static void append_cache(const char *path, int bucket, const dpk::SweepShape &sh, double us)
+{
+    if (!path) return;
+    FILE *f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "%d %s  # span (%d, %d], %.2f us per stage sweep of the tuning batch\n", bucket,
+            shape_str(sh).c_str(), 16 << bucket, 32 << bucket, us);
+    fclose(f);
+}
 
 extern "C" {
 
 int dp_batch_plan_create(dp_batch_plan **out, int n, const dp_problem *probs,
-                         const char *tune_cache, void *stream)
+                         const char *tune_cache, void *stream_)
 {
-    (void)out; (void)n; (void)probs; (void)tune_cache; (void)stream;
-    return DP_ENOTSUP;
+    if (!out) return fail(DP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || !probs) return fail(DP_EINVAL, "need n >= 1 problems");
+    (void)stream_;
+    dp_batch_plan *p = new (std::nothrow) dp_batch_plan;
+    if (!p) return fail(DP_ENOMEM, "plan allocation");
+    p->n = n;
+    p->probs.assign(probs, probs + n);
+    size_t total = 0;
+    for (int i = 0; i < n; ++i) {
+        int rc = validate_problem(&p->probs[i]);
+        if (rc != DP_OK) {
+            destroy_plan(p);
+            return fail(rc, "problem %d: %s", i, dp_last_error());
+        }
+        if (p->probs[i].flags != 0 || p->probs[i].ckpt_every != 0) {
+            destroy_plan(p);
+            return fail(DP_EINVAL, "problem %d: batched solves take no flags or checkpoints", i);
+        }
+        p->region.push_back(total);
+        total += solve_layout(&p->probs[i]).total;
+        p->Tmax = std::max(p->Tmax, p->probs[i].T);
+    }
+    int Kmax = 1;
+    for (auto &pb : p->probs) Kmax = std::max(Kmax, pb.K);
+    const size_t zoff = total;
+    total += 256 + sizeof(float) * (size_t)Kmax * (size_t)p->Tmax;   // zero prices for tuning
+    hipError_t e = hipMalloc(&p->ws, total);
+    if (e == hipSuccess) e = hipMemset(p->ws, 0, total);
+    if (e == hipSuccess) e = hipMalloc(&p->ddesc, sizeof(dpk::BatchDesc) * n);
+    if (e == hipSuccess) e = hipHostMalloc(&p->hstage, sizeof(dpk::BatchDesc) * n);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->staged, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        destroy_plan(p);
+        return hip_fail(e, "plan allocation");
+    }
+    p->ws_bytes = total;
+    const float *zeros_lam = reinterpret_cast<const float *>(p->ws + zoff);
+    p->hdesc.resize(n);
+    std::vector<dpk::ContractItem> citems;
+    for (int i = 0; i < n; ++i) {
+        const dp_problem &pb = p->probs[i];
+        const SolveLayout L = solve_layout(&pb);
+        char *base = p->ws + p->region[i];
+        dpk::BatchDesc &d = p->hdesc[i];
+        d.T = pb.T;
+        d.K = pb.K;
+        d.S = pb.st.S;
+        d.w_up = pb.st.w_up;
+        d.w_down = pb.st.w_down;
+        d.ld = L.Spad;
+        d.pay = {pb.st.delta, pb.st.eta_c, pb.st.eta_d, pb.st.c_deg, pb.st.c_start};
+        d.lam = nullptr;
+        d.P = nullptr;
+        d.V1 = nullptr;
+        d.pol = nullptr;
+        d.vbuf0 = reinterpret_cast<float *>(base + L.vA);
+        d.vbuf1 = reinterpret_cast<float *>(base + L.vB);
+        d.W = reinterpret_cast<float *>(base + L.W);
+        d.off = reinterpret_cast<double *>(base + L.off);
+        const int ntm = (pb.K + 15) / 16, ntn = (pb.st.S + 15) / 16;
+        for (int tn = 0; tn < ntn; ++tn)
+            for (int tm = 0; tm < ntm; ++tm) citems.push_back({i, tm, tn});
+    }
+    p->n_citems = (int)citems.size();
+    e = hipMalloc(&p->d_citems, sizeof(dpk::ContractItem) * citems.size());
+    if (e == hipSuccess)
+        e = hipMemcpy(p->d_citems, citems.data(), sizeof(dpk::ContractItem) * citems.size(),
+                      hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        destroy_plan(p);
+        return hip_fail(e, "expectation item table");
+    }
+
+    // Tile classes by span bucket.
+    std::map<int, std::vector<int>> buckets;
+    for (int i = 0; i < n; ++i)
+        buckets[span_bucket(p->probs[i].st.w_up + p->probs[i].st.w_down + 1)].push_back(i);
+    std::map<int, dpk::SweepShape> cached = read_cache(tune_cache);
+    int rc = DP_OK;
+    for (auto &kv : buckets) {
+        TileClass c;
+        c.inst = kv.second;
+        c.span_lo = (16 << kv.first) + 1;
+        c.span_hi = 32 << kv.first;
+        c.sh = pick_shape(&p->probs[c.inst[0]]);
+        auto it = cached.find(kv.first);
+        bool fits_all = true;
+        if (it != cached.end()) {
+            for (int i : c.inst) fits_all &= shape_fits(it->second, p->probs[i].st.w_up, p->probs[i].st.w_down);
+            if (fits_all) c.sh = it->second;
+        }
+        if (tune_cache && (it == cached.end() || !fits_all)) {
+            rc = autotune_class(p, c, zeros_lam);
+            if (rc != DP_OK) break;
+            append_cache(tune_cache, kv.first, c.sh, c.tuned_us);
+        }
+        for (int i : c.inst)
+            if (!shape_fits(c.sh, p->probs[i].st.w_up, p->probs[i].st.w_down)) {
+                rc = fail(DP_ENOTSUP, "problem %d: move window needs more LDS than a CU holds", i);
+                break;
+            }
+        if (rc != DP_OK) break;
+        p->classes.push_back(c);
+    }
+    if (rc == DP_OK) {
+        // merge classes that ended with the same shape (fewer launches per stage)
+        std::vector<TileClass> merged;
+        for (auto &c : p->classes) {
+            bool done = false;
+            for (auto &m : merged)
+                if (memcmp(&m.sh, &c.sh, sizeof c.sh) == 0) {
+                    m.inst.insert(m.inst.end(), c.inst.begin(), c.inst.end());
+                    m.span_lo = std::min(m.span_lo, c.span_lo);
+                    m.span_hi = std::max(m.span_hi, c.span_hi);
+                    done = true;
+                    break;
+                }
+            if (!done) merged.push_back(c);
+        }
+        p->classes = merged;
+        for (auto &c : p->classes) {
+            c.d_items = nullptr;
+            if ((rc = build_items(p, c)) != DP_OK) break;
+        }
+    }
+    if (rc == DP_OK) {
+        // capture the whole solve into a graph on the plan's stream
+        e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) rc = hip_fail(e, "begin capture");
+        if (rc == DP_OK) {
+            rc = enqueue_all(p, p->cap);
+            hipGraph_t g = nullptr;
+            e = hipStreamEndCapture(p->cap, &g);
+            if (rc == DP_OK && e != hipSuccess) rc = hip_fail(e, "end capture");
+            p->graph = g;
+        }
+        if (rc == DP_OK) {
+            e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) rc = hip_fail(e, "graph instantiate");
+        }
+    }
+    if (rc != DP_OK) {
+        destroy_plan(p);
+        return rc;
+    }
+    // description
+    char buf[512];
+    snprintf(buf, sizeof buf, "dp_batch_plan: %d instances, %d batch stages, %d expectation tiles, %zu bytes workspace\n",
+             n, p->Tmax, p->n_citems, p->ws_bytes);
+    p->text = buf;
+    for (auto &c : p->classes) {
+        snprintf(buf, sizeof buf, "  class span %d..%d: shape R=%d D=%d NW=%d NSPLIT=%d, %zu instances, %zu blocks/stage, %zu B LDS%s\n",
+                 c.span_lo, c.span_hi, c.sh.R, c.sh.D, c.sh.NW, c.sh.NSPLIT, c.inst.size(),
+                 c.items.size(), c.lds, c.tuned_us >= 0 ? " (autotuned)" : "");
+        p->text += buf;
+    }
+    *out = p;
+    return DP_OK;
 }
 
-int dp_batch_solve(dp_batch_plan *plan, const float *const *lam, const float *const *P,
-                   float *const *V1, int16_t *const *policy, void *stream)
+static int check_ptrs(dp_batch_plan *p, const float *const *lam, const float *const *P,
+                      float *const *V1, int16_t *const *policy)
 {
-    (void)plan; (void)lam; (void)P; (void)V1; (void)policy; (void)stream;
-    return DP_ENOTSUP;
+    if (!p) return fail(DP_EINVAL, "plan is NULL");
+    if (!lam || !P || !V1) return fail(DP_EINVAL, "lam, P and V1 arrays must be non-NULL");
+    for (int i = 0; i < p->n; ++i) {
+        if (!lam[i] || !P[i] || !V1[i]) return fail(DP_EINVAL, "instance %d: NULL pointer", i);
+        if (policy && !policy[i]) return fail(DP_EINVAL, "instance %d: NULL policy pointer", i);
+    }
+    return DP_OK;
 }
 
-int dp_batch_solve_looped(dp_batch_plan *plan, const float *const *lam, const float *const *P,
-                          float *const *V1, int16_t *const *policy, void *stream)
+int dp_batch_solve(dp_batch_plan *p, const float *const *lam, const float *const *P,
+                   float *const *V1, int16_t *const *policy, void *stream_)
 {
-    (void)plan; (void)lam; (void)P; (void)V1; (void)policy; (void)stream;
-    return DP_ENOTSUP;
+    int rc = check_ptrs(p, lam, P, V1, policy);
+    if (rc != DP_OK) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream_);
+    hipError_t e = hipSuccess;
+    if (p->staged_pending) e = hipEventSynchronize(p->staged);   // staging buffer free again
+    if (e != hipSuccess) return hip_fail(e, "staging wait");
+    for (int i = 0; i < p->n; ++i) {
+        p->hstage[i] = p->hdesc[i];
+        p->hstage[i].lam = lam[i];
+        p->hstage[i].P = P[i];
+        p->hstage[i].V1 = V1[i];
+        p->hstage[i].pol = policy ? policy[i] : nullptr;
+    }
+    e = hipMemcpyAsync(p->ddesc, p->hstage, sizeof(dpk::BatchDesc) * p->n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipEventRecord(p->staged, s);
+    if (e != hipSuccess) return hip_fail(e, "descriptor upload");
+    p->staged_pending = true;
+    e = hipGraphLaunch(p->exec, s);
+    if (e != hipSuccess) return hip_fail(e, "graph launch");
+    return DP_OK;
 }
 
-int dp_batch_plan_describe(const dp_batch_plan *plan, char *buf, size_t len)
+int dp_batch_solve_looped(dp_batch_plan *p, const float *const *lam, const float *const *P,
+                          float *const *V1, int16_t *const *policy, void *stream_)
 {
-    (void)plan; (void)buf; (void)len;
-    return DP_ENOTSUP;
+    int rc = check_ptrs(p, lam, P, V1, policy);
+    if (rc != DP_OK) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream_);
+    for (int i = 0; i < p->n; ++i) {
+        StageOutputs o = {};
+        o.v1 = V1[i];
+        o.pol = policy ? policy[i] : nullptr;
+        rc = run_stages(&p->probs[i], 1, p->probs[i].T, lam[i], P[i], nullptr, nullptr, o,
+                        p->ws + p->region[i], s);
+        if (rc != DP_OK) return rc;
+    }
+    return DP_OK;
 }
 
-void dp_batch_plan_destroy(dp_batch_plan *plan) { (void)plan; }
-
+int dp_batch_plan_describe(const dp_batch_plan *p, char *buf, size_t len)
+{
+    if (!p || !buf || len == 0) return fail(DP_EINVAL, "plan and buffer must be non-NULL");
+    snprintf(buf, len, "%s", p->text.c_str());
+    return DP_OK;
 }
+
+void dp_batch_plan_destroy(dp_batch_plan *p) { destroy_plan(p); }
+
+}  // extern "C"

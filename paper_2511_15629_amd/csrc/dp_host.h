@@ -1,0 +1,32 @@
+// Host-side helpers shared by the single-solve and batched translation units.
+#pragma once
+#include "dp_internal.h"
+#include "dpgpu.h"
+
+namespace dpgpu {
+
+int fail(int code, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+int validate_problem(const dp_problem *pb);
+dpk::SweepShape pick_shape(const dp_problem *pb);
+
+struct SolveLayout {
+    int Spad;
+    size_t vA, vB, W, off, flag, total;
+};
+SolveLayout solve_layout(const dp_problem *pb);
+
+struct StageOutputs {
+    float *vall;         // [(t_hi - t_lo + 2)][K][S] absolute values, slice t - t_lo (nullable)
+    float *v1;           // [K][S] absolute values of stage t_lo (nullable)
+    int16_t *pol;        // [(t_hi - t_lo + 1)][K][S] (nullable)
+    float *ckpt_v;       // checkpoint slots (nullable)
+    double *ckpt_off;
+    int ckpt_every;
+};
+
+int run_stages(const dp_problem *pb, int t_lo, int t_hi, const float *lam, const float *P,
+               const float *v_src, const double *off_src, const StageOutputs &out, void *ws,
+               hipStream_t stream);
+
+}  // namespace dpgpu

@@ -33,6 +33,31 @@ struct SweepShape {
     int R, D, NW, NSPLIT;    // outputs per lane, chunk of moves, waves per block, move splits
 };
 
+// Batched solves: one descriptor per instance, flattened work lists.
+struct BatchDesc {
+    int T, K, S, w_up, w_down, ld;
+    Payoff pay;
+    const float *lam;        // [T][K]
+    const float *P;          // [T][K][K]
+    float *V1;               // [K][S] absolute values of stage 1
+    int16_t *pol;            // [T][K][S] or null
+    float *vbuf0, *vbuf1;    // normalised values ping-pong [K][ld]
+    float *W;                // expectation [K][ld]
+    double *off;             // offsets C_t, t = 1..T+1
+};
+struct SweepItem {
+    int inst, k, tile;
+};
+struct ContractItem {
+    int inst, tm, tn;
+};
+
+hipError_t launch_batched_init(const BatchDesc *desc, int n, hipStream_t stream);
+hipError_t launch_batched_contract(const BatchDesc *desc, const ContractItem *items, int n,
+                                   int tau, hipStream_t stream);
+hipError_t launch_batched_sweep(const BatchDesc *desc, const SweepItem *items, int n, int tau,
+                                const SweepShape &sh, size_t lds, hipStream_t stream);
+
 // Stage kernels (launchers; all asynchronous on `stream`).
 hipError_t launch_contract(const float *A, bool transA, const float *B, int ldb, float *C,
                            int ldc, int K, int N, hipStream_t stream);

@@ -35,23 +35,20 @@ __device__ __forceinline__ float move_reward(float lam, int d, const Payoff &p)
 // Expectation C = A * B on MFMA (v_mfma_f32_16x16x4_f32, FP32 products and accumulation).
 // A is K x K (P_t, or its transpose), B is K x N with leading dimension ldb, C is K x N.
 // One wave computes one 16 x 16 tile of C; the reduction over K runs in chunks of
-// CH = 32 MFMA steps (128 terms) whose operands are all loaded before the chunk's
-// MFMA chain starts, so a chunk costs one memory round trip, not one per step.
+// CH MFMA steps (4 CH terms) whose operands are all loaded before the chunk's MFMA
+// chain starts, so a chunk costs one memory round trip, not one per step.  A single
+// solve has few tiles per stage and is latency-bound (CH = 32: one round trip up to
+// K = 128); a batch has tens of thousands of tiles in flight (CH = 8: fewer registers,
+// no wasted predicated loads for small K).
 // Lane layout of the 16x16x4 instruction: A[i][kk] from lane i + 16 kk, B[kk][j] from
 // lane j + 16 kk, result row 4 (lane / 16) + v, column lane % 16 in register v.
 // ------------------------------------------------------------------------------------
-template <bool TRANS_A>
-__global__ __launch_bounds__(256) void contract_kernel(const float *__restrict__ A,
-                                                       const float *__restrict__ B, int ldb,
-                                                       float *__restrict__ C, int ldc, int K,
-                                                       int N)
+template <bool TRANS_A, int CH = 32>
+__device__ __forceinline__ void contract_tile(const float *__restrict__ A,
+                                              const float *__restrict__ B, int ldb,
+                                              float *__restrict__ C, int ldc, int K, int N,
+                                              int tm, int tn)
 {
-    constexpr int CH = 32;
-    const int ntm = (K + 15) >> 4;
-    const int ntn = (N + 15) >> 4;
-    const int wid = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (wid >= ntm * ntn) return;
-    const int tm = wid % ntm, tn = wid / ntm;
     const int lane = threadIdx.x & 63;
     const int arow = tm * 16 + (lane & 15);
     const int kq = lane >> 4;
@@ -79,6 +76,19 @@ __global__ __launch_bounds__(256) void contract_kernel(const float *__restrict__
             if (r < K) C[(size_t)r * ldc + col] = acc[v];
         }
     }
+}
+
+template <bool TRANS_A>
+__global__ __launch_bounds__(256) void contract_kernel(const float *__restrict__ A,
+                                                       const float *__restrict__ B, int ldb,
+                                                       float *__restrict__ C, int ldc, int K,
+                                                       int N)
+{
+    const int ntm = (K + 15) >> 4;
+    const int ntn = (N + 15) >> 4;
+    const int wid = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wid >= ntm * ntn) return;
+    contract_tile<TRANS_A>(A, B, ldb, C, ldc, K, N, wid % ntm, wid / ntm);
 }
 
 hipError_t launch_contract(const float *A, bool transA, const float *B, int ldb, float *C,
@@ -113,15 +123,14 @@ hipError_t launch_contract(const float *A, bool transA, const float *B, int ldb,
 // within it" is the smallest next state attaining the maximum.
 // ------------------------------------------------------------------------------------
 template <int R, int D, int NW, int NSPLIT>
-__global__ __launch_bounds__(NW * 64) void sweep_kernel(SweepArgs a)
+__device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, const int tile)
 {
     constexpr int NS = NW / NSPLIT;
     constexpr int TS = 64 * R * NS;
     extern __shared__ float4 smem4[];
     float *smem = reinterpret_cast<float *>(smem4);
 
-    const int k = blockIdx.y;
-    const int s0 = blockIdx.x * TS;
+    const int s0 = tile * TS;
     const int S = a.S;
     const int s_end = min(s0 + TS, S);
     const int dlo = max(-a.w_down, -(s_end - 1));
@@ -228,10 +237,16 @@ __global__ __launch_bounds__(NW * 64) void sweep_kernel(SweepArgs a)
         if (a.pol) a.pol[idx] = (int16_t)j;
         if (a.ckpt_v) a.ckpt_v[idx] = vn;
     }
-    if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) {
+    if (k == 0 && tile == 0 && tid == 0) {
         a.off_cur[0] = Ct;
         if (a.ckpt_off) a.ckpt_off[0] = Ct;
     }
+}
+
+template <int R, int D, int NW, int NSPLIT>
+__global__ __launch_bounds__(NW * 64) void sweep_kernel(SweepArgs a)
+{
+    sweep_block<R, D, NW, NSPLIT>(a, blockIdx.y, blockIdx.x);
 }
 
 int sweep_tile(const SweepShape &sh) { return 64 * sh.R * (sh.NW / sh.NSPLIT); }
@@ -254,7 +269,11 @@ size_t sweep_lds_bytes(const SweepShape &sh, int w_up, int w_down)
     X(8, 8, 4, 4)          \
     X(4, 8, 4, 2)          \
     X(8, 16, 4, 2)         \
-    X(4, 16, 8, 4)
+    X(4, 16, 8, 4)         \
+    X(8, 8, 4, 1)          \
+    X(4, 8, 4, 1)          \
+    X(8, 16, 4, 1)         \
+    X(4, 16, 4, 1)
 
 bool sweep_shape_supported(const SweepShape &sh)
 {
@@ -275,6 +294,95 @@ hipError_t launch_sweep(const SweepArgs &a, const SweepShape &sh, hipStream_t st
         hipLaunchKernelGGL((sweep_kernel<r, d, nw, ns>), grid, dim3(nw * 64), lds, stream, \
                            a);                                                           \
         return hipGetLastError();                                                        \
+    }
+    DP_SWEEP_SHAPES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------------------------------
+// Batched solves: every launch covers one batch stage tau of all instances; instance i
+// is at its own stage t = T_i - tau + 1 (inactive once t < 1).  The same tile functions
+// as the single solve, with arguments taken from the instance descriptor.
+// ------------------------------------------------------------------------------------
+template <int R, int D, int NW, int NSPLIT>
+__global__ __launch_bounds__(NW * 64) void batched_sweep_kernel(const BatchDesc *__restrict__ desc,
+                                                                const SweepItem *__restrict__ items,
+                                                                int tau)
+{
+    const SweepItem it = items[blockIdx.x];
+    const BatchDesc d = desc[it.inst];
+    const int t = d.T - tau + 1;
+    if (t < 1) return;
+    SweepArgs a;
+    a.W = d.W;
+    a.ldw = d.ld;
+    a.lam = d.lam + (size_t)(t - 1) * d.K;
+    a.K = d.K;
+    a.S = d.S;
+    a.w_up = d.w_up;
+    a.w_down = d.w_down;
+    a.pay = d.pay;
+    const int cur = (d.T - t) & 1;
+    a.vprev = cur ? d.vbuf1 : d.vbuf0;
+    a.vnorm = cur ? d.vbuf0 : d.vbuf1;
+    a.ldv = d.ld;
+    a.off_next = d.off + (t + 1);
+    a.off_cur = d.off + t;
+    a.vabs = (t == 1) ? d.V1 : nullptr;
+    a.pol = d.pol ? d.pol + (size_t)(t - 1) * d.K * d.S : nullptr;
+    a.ckpt_v = nullptr;
+    a.ckpt_off = nullptr;
+    sweep_block<R, D, NW, NSPLIT>(a, it.k, it.tile);
+}
+
+__global__ __launch_bounds__(256) void batched_contract_kernel(const BatchDesc *__restrict__ desc,
+                                                               const ContractItem *__restrict__ items,
+                                                               int n, int tau)
+{
+    const int wid = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wid >= n) return;
+    const ContractItem it = items[wid];
+    const BatchDesc d = desc[it.inst];
+    const int t = d.T - tau + 1;
+    if (t < 1) return;
+    const float *vin = ((d.T - t) & 1) ? d.vbuf1 : d.vbuf0;
+    contract_tile<false, 8>(d.P + (size_t)(t - 1) * d.K * d.K, vin, d.ld, d.W, d.ld, d.K, d.S,
+                            it.tm, it.tn);
+}
+
+__global__ void batched_init_kernel(const BatchDesc *__restrict__ desc)
+{
+    const BatchDesc d = desc[blockIdx.y];
+    const size_t n = (size_t)d.K * d.ld;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        d.vbuf0[i] = 0.0f;
+    if (blockIdx.x == 0 && threadIdx.x == 0) d.off[d.T + 1] = 0.0;
+}
+
+hipError_t launch_batched_init(const BatchDesc *desc, int n, hipStream_t stream)
+{
+    hipLaunchKernelGGL(batched_init_kernel, dim3(64, n), dim3(256), 0, stream, desc);
+    return hipGetLastError();
+}
+
+hipError_t launch_batched_contract(const BatchDesc *desc, const ContractItem *items, int n,
+                                   int tau, hipStream_t stream)
+{
+    hipLaunchKernelGGL(batched_contract_kernel, dim3((n + 3) / 4), dim3(256), 0, stream, desc,
+                       items, n, tau);
+    return hipGetLastError();
+}
+
+hipError_t launch_batched_sweep(const BatchDesc *desc, const SweepItem *items, int n, int tau,
+                                const SweepShape &sh, size_t lds, hipStream_t stream)
+{
+#define X(r, d, nw, ns)                                                                      \
+    if (sh.R == r && sh.D == d && sh.NW == nw && sh.NSPLIT == ns) {                          \
+        hipLaunchKernelGGL((batched_sweep_kernel<r, d, nw, ns>), dim3(n), dim3(nw * 64), lds, \
+                           stream, desc, items, tau);                                        \
+        return hipGetLastError();                                                            \
     }
     DP_SWEEP_SHAPES(X)
 #undef X

@@ -1,0 +1,142 @@
+"""GPU tests of the batched solve (dp_batch_* through the C ABI).
+
+The batched path must give bitwise the same V_1 and policies as one dp_solve per
+instance (the looped path), whatever tile classes the plan picks, and match the oracle.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from parity import RTOL, _mismatch, value_error
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2511_15629_amd as m
+    return m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def small_batch():
+    specs = [
+        (1, 6, 3, 50, 5, 7, {}), (2, 6, 17, 300, 30, 45, {}), (3, 9, 20, 700, 60, 90, dict(c_start=2.0)),
+        (4, 4, 5, 129, 128, 128, {}), (5, 6, 1, 10, 2, 3, {}), (6, 12, 8, 257, 3, 1, {}),
+        (7, 6, 33, 600, 250, 250, dict(lam_lo=-150.0)), (8, 5, 12, 1001, 14, 18, dict(eta=0.86)),
+        (9, 6, 2, 2, 1, 1, {}), (10, 7, 64, 512, 0, 0, {}),
+    ]
+    return [wl.random_small(sd, T, K, S, wu, wd, **kw) for (sd, T, K, S, wu, wd, kw) in specs]
+
+
+def run_batch(dp, plan, insts, looped=False, lam_override=None):
+    lams = [dev(i.lam if lam_override is None else lam_override[n]) for n, i in enumerate(insts)]
+    Ps = [dev(i.P) for i in insts]
+    V1 = [torch.full((i.K, i.storage.S), float("nan"), device="cuda") for i in insts]
+    pol = [torch.full((i.T, i.K, i.storage.S), -1, dtype=torch.int16, device="cuda") for i in insts]
+    plan.solve(lams, Ps, V1, pol, looped=looped)
+    torch.cuda.synchronize()
+    return V1, pol
+
+
+def test_batched_equals_looped_bitwise_and_matches_oracle(dp):
+    insts = small_batch()
+    plan = dp.BatchPlan([(i.T, i.K, i.storage) for i in insts])
+    print(plan.describe())
+    Vb, pb = run_batch(dp, plan, insts)
+    Vl, pl = run_batch(dp, plan, insts, looped=True)
+    for n, inst in enumerate(insts):
+        assert torch.equal(Vb[n], Vl[n]), inst.name
+        assert torch.equal(pb[n], pl[n]), inst.name
+        ref = oracle.solve(inst.storage, inst.lam, inst.P)
+        assert value_error(Vb[n].cpu().numpy(), ref["V"][0]) <= RTOL, inst.name
+        pol = pb[n].cpu().numpy()
+        for t in range(1, inst.T + 1):
+            if not np.array_equal(pol[t - 1], ref["policy"][t - 1]):
+                _mismatch(inst.storage, inst.lam[t - 1], inst.P[t - 1], ref["V"][t],
+                          ref["V"][t - 1], pol[t - 1], ref["policy"][t - 1],
+                          f"{inst.name} stage {t}")
+    plan.close()
+
+
+def test_replay_with_new_pointers_and_data(dp):
+    insts = small_batch()[:5]
+    plan = dp.BatchPlan([(i.T, i.K, i.storage) for i in insts])
+    run_batch(dp, plan, insts)
+    rng = np.random.default_rng(7)
+    lam2 = [wl.f32(i.lam.astype(np.float64) + rng.normal(0, 10, i.lam.shape)) for i in insts]
+    Vb, pb = run_batch(dp, plan, insts, lam_override=lam2)
+    for n, inst in enumerate(insts):
+        out = dp.solve(dev(lam2[n]), dev(inst.P), inst.storage, store_all=False, policy=True)
+        torch.cuda.synchronize()
+        assert torch.equal(Vb[n], out["V"]) and torch.equal(pb[n], out["policy"])
+    plan.close()
+
+
+def test_autotuned_plan_is_bitwise_equal_and_cache_is_reused(dp, tmp_path):
+    insts = small_batch()
+    cache = str(tmp_path / "tune.txt")
+    plan = dp.BatchPlan([(i.T, i.K, i.storage) for i in insts], tune_cache=cache)
+    text = plan.describe()
+    print(text)
+    assert "autotuned" in text and os.path.exists(cache)
+    Vb, pb = run_batch(dp, plan, insts)
+    plan.close()
+    lines = open(cache).read().splitlines()
+    plan2 = dp.BatchPlan([(i.T, i.K, i.storage) for i in insts], tune_cache=cache)
+    assert "autotuned" not in plan2.describe()
+    assert open(cache).read().splitlines() == lines
+    Vl, pl = run_batch(dp, plan2, insts, looped=True)
+    for n in range(len(insts)):
+        assert torch.equal(Vb[n], Vl[n]) and torch.equal(pb[n], pl[n])
+    plan2.close()
+
+
+def test_fleet_of_512_batched_equals_looped(dp):
+    insts = wl.fleet_5min()
+    plan = dp.BatchPlan([(i.T, i.K, i.storage) for i in insts])
+    print(plan.describe())
+    cache = {}
+    lams = [dev(i.lam) for i in insts]
+    Ps = []
+    for i in insts:
+        if id(i.P) not in cache:
+            cache[id(i.P)] = dev(i.P)
+        Ps.append(cache[id(i.P)])
+    Vb = [torch.empty(i.K, i.storage.S, device="cuda") for i in insts]
+    Vl = [torch.empty(i.K, i.storage.S, device="cuda") for i in insts]
+    plan.solve(lams, Ps, Vb, None)
+    plan.solve(lams, Ps, Vl, None, looped=True)
+    torch.cuda.synchronize()
+    for n in range(len(insts)):
+        assert torch.equal(Vb[n], Vl[n]), insts[n].name
+    # oracle parity of V_1 on the three smallest instances
+    order = sorted(range(len(insts)), key=lambda n: insts[n].candidates())[:3]
+    for n in order:
+        inst = insts[n]
+        ref = oracle.solve(inst.storage, inst.lam, inst.P, keep_all=False, want_policy=False)
+        v = Vb[n].cpu().numpy().astype(np.float64)
+        err = np.abs(v - ref["V1"]).max() / np.abs(ref["V1"]).max()
+        assert err <= 1e-5, (inst.name, err)
+    plan.close()
+
+
+def test_plan_rejects_flags(dp):
+    inst = wl.random_small(1, 3, 2, 10, 1, 1)
+    from paper_2511_15629_amd import _lib
+    import ctypes
+    pb = _lib.make_problem(3, 2, inst.storage, _lib.DP_STORE_V_ALL)
+    arr = (_lib.Problem * 1)(pb)
+    h = ctypes.c_void_p()
+    rc = _lib.lib().dp_batch_plan_create(ctypes.byref(h), 1, arr, None, None)
+    assert rc == -1 and not h.value
