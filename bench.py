@@ -174,6 +174,9 @@ def main():
     ap.add_argument("--workload", default="day_5min")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after the steps, copy 256 MiB device-to-device once (a kernel of known "
+                         "traffic for calibrating hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the solver runs on a single GPU (asked for {args.gpus}); batches "
@@ -202,6 +205,12 @@ def main():
                    "outputs": "V_1 f32 + all int16 policies", "parallelism": "single GPU"},
         "roofline": roofline_of(inst, timing),
     }
+    if args.copy_probe:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        line["copy_probe_bytes"] = src.numel() * 4
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(inst)
     if not args.no_extra:

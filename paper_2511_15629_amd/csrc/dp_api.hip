@@ -157,6 +157,7 @@ int run_stages(const dp_problem *pb, int t_lo, int t_hi, const float *lam, const
                                              off + (t_hi + 1), vabs_term, stream);
     if (e != hipSuccess) return hip_fail(e, "init_terminal");
 
+    const int E = out.ckpt_every > 0 ? out.ckpt_every : 16;
     const dpk::SweepShape sh = pick_shape(pb);
     if (!dpk::sweep_shape_supported(sh)) return fail(DP_EINVAL, "unsupported sweep shape");
     if (dpk::sweep_lds_bytes(sh, pb->st.w_up, pb->st.w_down) > 160 * 1024)
@@ -171,7 +172,6 @@ int run_stages(const dp_problem *pb, int t_lo, int t_hi, const float *lam, const
     a.pay = {pb->st.delta, pb->st.eta_c, pb->st.eta_d, pb->st.c_deg, pb->st.c_start};
     a.W = Wb;
     a.ldv = L.Spad;
-    const int E = out.ckpt_every > 0 ? out.ckpt_every : 16;
     int cur = 0;
     for (int t = t_hi; t >= t_lo; --t) {
         const float *vin = vbuf[cur];
@@ -182,7 +182,6 @@ int run_stages(const dp_problem *pb, int t_lo, int t_hi, const float *lam, const
         if (e != hipSuccess) return hip_fail(e, "contract");
         if ((e = timer_mark(stream, 1, false)) != hipSuccess) return hip_fail(e, "timer");
         a.lam = lam + (size_t)(t - 1) * K;
-        a.vprev = vin;
         a.off_next = off + (t + 1);
         a.off_cur = off + t;
         a.vnorm = vout;
@@ -339,7 +338,7 @@ int dp_solve(const dp_problem *pb, const float *lam, const float *P, const float
 // ------------------------------------------------------------------------------------
 struct AdjLayout {
     int Spad;
-    size_t mu, nu, vseg, polseg, solve_ws, total;
+    size_t mu, nu, scale, vseg, polseg, solve_ws, total;
 };
 
 static AdjLayout adj_layout(const dp_problem *pb, bool ckpt_mode)
@@ -350,6 +349,7 @@ static AdjLayout adj_layout(const dp_problem *pb, bool ckpt_mode)
     size_t o = 0;
     L.mu = o; o += plane;
     L.nu = o; o += plane;
+    L.scale = o; o += 256;
     if (ckpt_mode) {
         const int E = pb->ckpt_every > 0 ? pb->ckpt_every : 16;
         const size_t KS = (size_t)pb->K * pb->st.S;
@@ -393,8 +393,11 @@ int dp_adjoint(const dp_problem *pb, const float *lam, const float *P, const flo
     float *nu = reinterpret_cast<float *>(base + L.nu);
     const size_t KS = (size_t)K * S;
     const dpk::Payoff pay = {pb->st.delta, pb->st.eta_c, pb->st.eta_d, pb->st.c_deg, pb->st.c_start};
+    double *scale = reinterpret_cast<double *>(base + L.scale);
     hipError_t e = dpk::launch_copy_rows(seed, S, mu, L.Spad, K, S, stream);
     if (e != hipSuccess) return hip_fail(e, "seed copy");
+    e = dpk::launch_adjoint_scale(seed, KS, scale, stream);
+    if (e != hipSuccess) return hip_fail(e, "adjoint scale");
 
     const int E = ckpt_mode ? pb->ckpt_every : T;
     float *cv = nullptr;
@@ -432,14 +435,12 @@ int dp_adjoint(const dp_problem *pb, const float *lam, const float *P, const flo
         for (int t = t_lo; t <= t_hi; ++t) {
             const int16_t *pol_t = pseg + (size_t)(t - t_lo) * KS;
             const float *Vn = Vseg + (size_t)(t + 1 - t_lo) * KS;
-            e = dpk::launch_pushforward(mu, L.Spad, pol_t, K, S, pay, nu, L.Spad,
+            e = dpk::launch_pushforward(mu, L.Spad, pol_t, K, S, pay, scale, nu, L.Spad,
                                         grad_lam + (size_t)(t - 1) * K, stream);
             if (e != hipSuccess) return hip_fail(e, "pushforward");
-            e = dpk::launch_gradP(nu, L.Spad, Vn, K, S, grad_P + (size_t)(t - 1) * K * K, stream);
-            if (e != hipSuccess) return hip_fail(e, "gradP");
-            e = dpk::launch_contract(P + (size_t)(t - 1) * K * K, true, nu, L.Spad, mu, L.Spad, K,
-                                     S, stream);
-            if (e != hipSuccess) return hip_fail(e, "transport");
+            e = dpk::launch_adjoint_mix(nu, L.Spad, Vn, K, S, P + (size_t)(t - 1) * K * K,
+                                        grad_P + (size_t)(t - 1) * K * K, mu, L.Spad, stream);
+            if (e != hipSuccess) return hip_fail(e, "gradP/transport");
         }
     }
     if (grad_vterm) {

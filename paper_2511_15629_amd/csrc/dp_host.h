@@ -11,7 +11,7 @@ int validate_problem(const dp_problem *pb);
 dpk::SweepShape pick_shape(const dp_problem *pb);
 
 struct SolveLayout {
-    int Spad;
+    int Spad;                 // row stride of the value planes and the W plane
     size_t vA, vB, W, off, flag, total;
 };
 SolveLayout solve_layout(const dp_problem *pb);

@@ -13,12 +13,11 @@ struct Payoff {
 // One stage of the Bellman sweep (Eq. (5)): inputs W_t (expectation) and lam_t,
 // outputs the normalised values, optional absolute values, policies, checkpoint.
 struct SweepArgs {
-    const float *W;          // [K][ldw] expectation W_t
+    const float *W;          // [K][ldw] expectation W_t; W[0] is the stage's normalisation
     int ldw;
     const float *lam;        // [K]
     int K, S, w_up, w_down;
     Payoff pay;
-    const float *vprev;      // normalised V_{t+1} (its [0][0] entry is this stage's shift)
     const double *off_next;  // C_{t+1}
     double *off_cur;         // C_t (written by block (0,0))
     float *vnorm;            // out [K][ldv] normalised V_t = U - shift
@@ -74,10 +73,12 @@ hipError_t launch_init_terminal(const float *src, const double *src_off, int K, 
 
 // Adjoint stage kernels.
 hipError_t launch_pushforward(const float *mu, int ldm, const int16_t *pol, int K, int S,
-                              Payoff pay, float *nu, int ldn, float *grad_lam,
+                              Payoff pay, const double *scale, float *nu, int ldn,
+                              float *grad_lam, hipStream_t stream);
+hipError_t launch_adjoint_scale(const float *seed, size_t n, double *scale, hipStream_t stream);
+hipError_t launch_adjoint_mix(const float *nu, int ldn, const float *V, int K, int S,
+                              const float *Pt, float *gP, float *mu, int ldm,
                               hipStream_t stream);
-hipError_t launch_gradP(const float *nu, int ldn, const float *V, int K, int S,
-                        float *gP, hipStream_t stream);
 hipError_t launch_copy_rows(const float *src, int lds, float *dst, int ldd, int K, int S,
                             hipStream_t stream);
 hipError_t launch_fill(float *dst, size_t n, float v, hipStream_t stream);

@@ -24,11 +24,17 @@ __device__ __forceinline__ float move_energy(int d, const Payoff &p)
     return 0.0f;
 }
 
+// Price-independent part of the payoff: h(d) = -c_deg |g(d)| - c_start [d != 0].
+__device__ __forceinline__ float move_cost(int d, const Payoff &p)
+{
+    const float h = -(p.c_deg * fabsf(move_energy(d, p)));
+    return d != 0 ? h - p.c_start : h;
+}
+
+// r(lam, d) = lam g(d) + h(d), one fused multiply-add (the same rounding in every kernel).
 __device__ __forceinline__ float move_reward(float lam, int d, const Payoff &p)
 {
-    float g = move_energy(d, p);
-    float r = lam * g - p.c_deg * fabsf(g);
-    return d != 0 ? r - p.c_start : r;
+    return fmaf(lam, move_energy(d, p), move_cost(d, p));
 }
 
 // ------------------------------------------------------------------------------------
@@ -208,7 +214,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
     }
     __syncthreads();
 
-    const float shift = a.vprev[0];
+    const float shift = a.W[0];    // W_t[0][0]: this stage's normalisation constant
     const double Ct = a.off_next[0] + (double)shift;
     for (int o = tid; o < TS; o += NW * 64) {
         const int s = s0 + o;
@@ -324,7 +330,6 @@ __global__ __launch_bounds__(NW * 64) void batched_sweep_kernel(const BatchDesc 
     a.w_down = d.w_down;
     a.pay = d.pay;
     const int cur = (d.T - t) & 1;
-    a.vprev = cur ? d.vbuf1 : d.vbuf0;
     a.vnorm = cur ? d.vbuf0 : d.vbuf1;
     a.ldv = d.ld;
     a.off_next = d.off + (t + 1);
@@ -422,73 +427,46 @@ hipError_t launch_init_terminal(const float *src, const double *src_off, int K, 
 
 // ------------------------------------------------------------------------------------
 // Adjoint: push the occupation measure through the policy (deterministic).
-// Block = one price state k, 4 waves; wave w owns a contiguous quarter of the SoC range
-// and its own LDS accumulator nu_w[S].  Each 64-lane chunk is bitonic-sorted by
-// (next state j, lane), a segmented scan sums the masses of equal j in lane order, and
-// the last lane of every segment adds the segment sum into nu_w[j] (one writer per j
-// per chunk, chunks in ascending s).  Finally nu = nu_0 + nu_1 + nu_2 + nu_3 in that
-// order.  grad_lam[k] = sum_s mu[s] g(pi(s) - s), per-lane then a fixed-order tree.
+//
+// nu_t[k][j] = sum_{s: pi_t[k][s] = j} mu_t[k][s] is accumulated in LDS as 64-bit fixed
+// point: each mass is scaled by a power of two 2^e (exact), rounded once to an integer,
+// and added with ds_add_u64.  Integer addition is associative, so the sums do not depend
+// on the order the lanes reach LDS.  2^e is chosen from a bound B on sum |mu| (the adjoint
+// is mass-preserving under row-stochastic P, so B = 2 sum |seed| bounds every stage):
+// 2^e B <= 2^61 keeps every partial sum inside int64, and the rounding of each mass is at
+// most 2^-62 B.  grad_lam[k] = sum_s mu[s] g(pi(s) - s) uses per-lane sums and a
+// fixed-order tree.  One block per price state.
 // ------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void pushforward_kernel(const float *__restrict__ mu,
-                                                          int ldm,
-                                                          const int16_t *__restrict__ pol,
-                                                          int K, int S, Payoff pay,
-                                                          float *__restrict__ nu, int ldn,
-                                                          float *__restrict__ grad_lam)
+__global__ __launch_bounds__(1024) void pushforward_kernel(const float *__restrict__ mu,
+                                                           int ldm,
+                                                           const int16_t *__restrict__ pol,
+                                                           int K, int S, Payoff pay,
+                                                           const double *__restrict__ scale,
+                                                           float *__restrict__ nu, int ldn,
+                                                           float *__restrict__ grad_lam)
 {
     extern __shared__ float4 smem4[];
-    float *acc = reinterpret_cast<float *>(smem4);      // [4][S]
-    __shared__ float red[256];
+    unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem4);   // [S]
+    __shared__ float red[1024];
     const int k = blockIdx.x;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    for (int i = tid; i < 4 * S; i += 256) acc[i] = 0.0f;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int i = tid; i < S; i += nt) acc[i] = 0ull;
     __syncthreads();
-    const int q = (((S + 3) / 4) + 63) & ~63;
-    const int sb = wave * q, se = min(S, sb + q);
-    float *my = acc + wave * S;
+    const double sc = scale[0];
     float gl = 0.0f;
-    for (int c = sb; c < se; c += 64) {
-        const int s = c + lane;
-        const bool valid = s < se;
-        const int j = valid ? (int)pol[(size_t)k * S + s] : 0x7fff;
-        const float m = valid ? mu[(size_t)k * ldm + s] : 0.0f;
-        if (valid) gl += m * move_energy(j - s, pay);
-        unsigned key = ((unsigned)j << 6) | (unsigned)lane;
-        float val = m;
-#pragma unroll
-        for (int kk = 2; kk <= 64; kk <<= 1) {
-#pragma unroll
-            for (int jj = kk >> 1; jj > 0; jj >>= 1) {
-                const unsigned okey = __shfl_xor(key, jj);
-                const float oval = __shfl_xor(val, jj);
-                const bool up = (lane & kk) == 0;
-                const bool lower = (lane & jj) == 0;
-                const bool take_min = (lower == up);
-                const bool other_smaller = okey < key;
-                const bool take_other = take_min ? other_smaller : !other_smaller;
-                if (take_other) {
-                    key = okey;
-                    val = oval;
-                }
-            }
-        }
-        const int myj = (int)(key >> 6);
-        float v = val;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const float pv = __shfl_up(v, off);
-            const int pj = __shfl_up(myj, off);
-            if (lane >= off && pj == myj) v += pv;
-        }
-        const int nj = __shfl_down(myj, 1);
-        const bool last = (lane == 63) || (nj != myj);
-        if (last && myj != 0x7fff) my[myj] += v;
+    for (int s = tid; s < S; s += nt) {
+        const int j = pol[(size_t)k * S + s];
+        const float m = mu[(size_t)k * ldm + s];
+        gl = fmaf(m, move_energy(j - s, pay), gl);
+        const long long q = llrint((double)m * sc);
+        atomicAdd(&acc[j], (unsigned long long)q);
     }
     red[tid] = gl;
     __syncthreads();
-    for (int i = tid; i < S; i += 256)
-        nu[(size_t)k * ldn + i] = ((acc[i] + acc[S + i]) + acc[2 * S + i]) + acc[3 * S + i];
-    for (int w = 128; w > 0; w >>= 1) {
+    const double inv = 1.0 / sc;
+    for (int i = tid; i < S; i += nt)
+        nu[(size_t)k * ldn + i] = (float)((double)(long long)acc[i] * inv);
+    for (int w = nt >> 1; w > 0; w >>= 1) {
         if (tid < w) red[tid] += red[tid + w];
         __syncthreads();
     }
@@ -496,43 +474,90 @@ __global__ __launch_bounds__(256) void pushforward_kernel(const float *__restric
 }
 
 hipError_t launch_pushforward(const float *mu, int ldm, const int16_t *pol, int K, int S,
-                              Payoff pay, float *nu, int ldn, float *grad_lam,
-                              hipStream_t stream)
+                              Payoff pay, const double *scale, float *nu, int ldn,
+                              float *grad_lam, hipStream_t stream)
 {
-    const size_t lds = sizeof(float) * 4 * (size_t)S;
-    hipLaunchKernelGGL(pushforward_kernel, dim3(K), dim3(256), lds, stream, mu, ldm, pol, K,
-                       S, pay, nu, ldn, grad_lam);
+    const size_t lds = sizeof(unsigned long long) * (size_t)S;
+    const int nt = S >= 4096 ? 1024 : (S >= 1024 ? 512 : 256);
+    hipLaunchKernelGGL(pushforward_kernel, dim3(K), dim3(nt), lds, stream, mu, ldm, pol, K, S,
+                       pay, scale, nu, ldn, grad_lam);
+    return hipGetLastError();
+}
+
+// Power-of-two fixed-point scale for the push-forward from the seed:
+// B = 2 sum |seed| (fixed-order tree in one block), scale = 2^floor(log2(2^61 / B)).
+__global__ __launch_bounds__(1024) void adjoint_scale_kernel(const float *__restrict__ seed,
+                                                             size_t n, double *scale)
+{
+    __shared__ double red[1024];
+    double a = 0.0;
+    for (size_t i = threadIdx.x; i < n; i += 1024) a += fabs((double)seed[i]);
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double B = fmax(2.0 * red[0], 1e-300);
+        int e;
+        frexp(B, &e);                       // B < 2^e
+        scale[0] = ldexp(1.0, 61 - e);      // 2^(61 - e) B < 2^61
+    }
+}
+
+hipError_t launch_adjoint_scale(const float *seed, size_t n, double *scale, hipStream_t stream)
+{
+    hipLaunchKernelGGL(adjoint_scale_kernel, dim3(1), dim3(1024), 0, stream, seed, n, scale);
     return hipGetLastError();
 }
 
 // ------------------------------------------------------------------------------------
-// grad_P_t = nu_t V_{t+1}^T on MFMA: gP[k][k'] = sum_j nu[k][j] V[k'][j].
-// Block = one 16 x 16 output tile, 4 waves each reducing a contiguous quarter of j;
-// the four partial tiles are added in wave order.
+// One launch for the two products that consume nu_t:
+//   blocks [0, nG):  grad_P_t = nu_t V_{t+1}^T, one 16 x 16 tile per block, four waves
+//                    each reducing a quarter of j in chunks of prefetched MFMA steps,
+//                    the partial tiles added in wave order;
+//   blocks [nG, ..): mu_{t+1} = P_t^T nu_t, the expectation tile function with A = P^T.
 // ------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void gradP_kernel(const float *__restrict__ nu, int ldn,
-                                                    const float *__restrict__ V, int K, int S,
-                                                    float *__restrict__ gP)
+__global__ __launch_bounds__(256) void adjoint_mix_kernel(const float *__restrict__ nu, int ldn,
+                                                          const float *__restrict__ V, int K,
+                                                          int S, const float *__restrict__ Pt,
+                                                          float *__restrict__ gP,
+                                                          float *__restrict__ mu, int ldm,
+                                                          int nG)
 {
+    constexpr int CH = 16;
     __shared__ float part[4][256];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    if ((int)blockIdx.x >= nG) {
+        const int ntm = (K + 15) >> 4, ntn = (S + 15) >> 4;
+        const int wid = (blockIdx.x - nG) * 4 + wave;
+        if (wid >= ntm * ntn) return;
+        contract_tile<true, 32>(Pt, nu, ldn, mu, ldm, K, S, wid % ntm, wid / ntm);
+        return;
+    }
     const int ntm = (K + 15) >> 4;
     const int tm = blockIdx.x % ntm, tn = blockIdx.x / ntm;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int kq = lane >> 4;
     const int arow = tm * 16 + (lane & 15);   // k
     const int bcol = tn * 16 + (lane & 15);   // k'
+    const bool rok = arow < K, cok = bcol < K;
     const int steps = (S + 3) / 4;
     const int per = (steps + 3) / 4;
     const int jb = wave * per * 4, je = min(S, (wave + 1) * per * 4);
     floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-    for (int j0 = jb; j0 < je; j0 += 4) {
-        const int j = j0 + kq;
-        float av = 0.f, bv = 0.f;
-        if (j < je) {
-            if (arow < K) av = nu[(size_t)arow * ldn + j];
-            if (bcol < K) bv = V[(size_t)bcol * S + j];
+    for (int j0 = jb; j0 < je; j0 += 4 * CH) {
+        float av[CH], bv[CH];
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+            const int j = j0 + 4 * i + kq;
+            const bool jok = j < je;
+            av[i] = (jok && rok) ? nu[(size_t)arow * ldn + j] : 0.f;
+            bv[i] = (jok && cok) ? V[(size_t)bcol * S + j] : 0.f;
         }
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < CH; ++i)
+            if (j0 + 4 * i < je) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[i], acc, 0, 0, 0);
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) part[wave][(4 * kq + v) * 16 + (lane & 15)] = acc[v];
@@ -543,11 +568,15 @@ __global__ __launch_bounds__(256) void gradP_kernel(const float *__restrict__ nu
         gP[(size_t)kr * K + kc] = ((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid];
 }
 
-hipError_t launch_gradP(const float *nu, int ldn, const float *V, int K, int S, float *gP,
-                        hipStream_t stream)
+hipError_t launch_adjoint_mix(const float *nu, int ldn, const float *V, int K, int S,
+                              const float *Pt, float *gP, float *mu, int ldm, hipStream_t stream)
 {
     const int nt = (K + 15) / 16;
-    hipLaunchKernelGGL(gradP_kernel, dim3(nt * nt), dim3(256), 0, stream, nu, ldn, V, K, S, gP);
+    const int nG = nt * nt;
+    const int tiles = nt * ((S + 15) / 16);
+    const int nB = (tiles + 3) / 4;
+    hipLaunchKernelGGL(adjoint_mix_kernel, dim3(nG + nB), dim3(256), 0, stream, nu, ldn, V, K, S,
+                       Pt, gP, mu, ldm, nG);
     return hipGetLastError();
 }
 
