@@ -64,14 +64,38 @@ def timed_solves(dp, torch, inst, steps, warmup):
     return (t1 - t0) / steps, timing
 
 
-def roofline_of(inst, timing):
+HERE = os.path.dirname(os.path.abspath(__file__))
+TRAFFIC_FILE = os.path.join(HERE, "profiles", "sweep_traffic_day_5min.txt")
+KERNEL_SOURCE = os.path.join(HERE, "paper_2511_15629_amd", "csrc", "dp_kernels.hip")
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per sweep launch from the committed counter summary (two rocprofv3 --pmc
+    passes, calibrated on a copy of known size), or None when the summary is for another
+    workload or the kernel source has changed since the counters were taken."""
+    import hashlib
+    if workload != "day_5min" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    fields = {}
+    for line in open(TRAFFIC_FILE):
+        if not line.startswith("#") and ":" in line:
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    digest = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    if fields.get("kernel_source_sha256") != digest:
+        return None
+    return int(fields["bytes_per_launch"])
+
+
+def roofline_of(inst, timing, traffic=None):
     sweep_ms, n_sweep, exp_ms, n_exp = timing
     per_launch = inst.candidates() / inst.T            # candidates per sweep launch (avg)
     avg_s = sweep_ms / 1e3 / max(n_sweep, 1)
     achieved = per_launch / avg_s / 1e9
     return {
         "bound": "alu", "achieved": round(achieved, 1), "peak": round(SWEEP_PEAK_GUPD, 1),
-        "unit": "Gupd/s", "frac": round(achieved / SWEEP_PEAK_GUPD, 4), "traffic": None,
+        "unit": "Gupd/s", "frac": round(achieved / SWEEP_PEAK_GUPD, 4), "traffic": traffic,
+        "traffic_GBps": None if traffic is None else round(traffic / avg_s / 1e9, 1),
         "kernel": "sweep_kernel", "avg_launch_us": round(avg_s * 1e6, 3),
         "launches": n_sweep,
         "expectation_avg_launch_us": round(exp_ms / 1e3 / max(n_exp, 1) * 1e6, 3),
@@ -203,7 +227,7 @@ def main():
         "config": {"workload": inst.name, "T": inst.T, "K": inst.K, "S": st.S,
                    "w_up": st.w_up, "w_down": st.w_down, "candidates_per_step": cand,
                    "outputs": "V_1 f32 + all int16 policies", "parallelism": "single GPU"},
-        "roofline": roofline_of(inst, timing),
+        "roofline": roofline_of(inst, timing, measured_traffic(args.workload)),
     }
     if args.copy_probe:
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")

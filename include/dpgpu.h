@@ -149,6 +149,38 @@ int dp_adjoint(const dp_problem *pb, const float *lam, const float *P, const flo
                const float *seed, float *grad_lam, float *grad_P, float *grad_vterm,
                void *ws, size_t ws_bytes, void *stream);
 
+/* ---- Stagewise-independent prices on the paper's power-action grid ------------------
+ * The model of Sec. II-B solved exactly as Algorithm 1 prints it: at each stage t the price
+ * takes R sampled levels lam[t][r] with probabilities prob[t][r] (sum 1), independent of
+ * the past; the actions are the recombining power grid of Sec. III-A,
+ *   p_hat = [-p_bar, -(n_c-1) delta/eta, ..., -delta/eta, 0, delta eta, ..., (n_d-1) delta eta, p_bar],
+ *   n_c = ceil(p_bar eta / delta), n_d = ceil(p_bar / (delta eta)), P = n_c + n_d + 1,
+ * whose interior entries move the state of charge by whole grid steps and whose two
+ * endpoints are interpolated between the neighbouring grid values (Algorithm 1's next-state
+ * proxies, floor/ceil indices and interpolation factors, computed in FP64); pairs leaving
+ * [0, s_bar] are infeasible.  Payoff lam p (no costs).  For t = T..1:
+ *   Q_{t-1}(s, r) = max_p lam[t][r] p + V_t(s + F(p)),  V_{t-1}(s) = sum_r prob[t][r] Q_{t-1}(s, r),
+ * with V_T = 0.  FP32 arithmetic, same device-memory and stream conventions as above. */
+typedef struct dp_iid_problem {
+    int32_t T;           /* stages, >= 1                                                 */
+    int32_t R;           /* price samples per stage, 1 .. 4096                           */
+    int32_t S;           /* SoC grid points 0, delta, ..., (S-1) delta; 2 .. DP_MAX_S   */
+    int32_t reserved;    /* must be 0                                                    */
+    float delta;         /* MWh per grid step, > 0                                       */
+    float eta;           /* one-way efficiency, (0, 1]                                   */
+    float p_bar;         /* power capacity (MWh per stage), > 0                          */
+    uint32_t flags;      /* DP_STORE_V_ALL                                               */
+} dp_iid_problem;
+
+/* Action-grid sizes of the problem (host only, no GPU use). */
+int dp_iid_action_grid(const dp_iid_problem *pb, int *P, int *n_c, int *n_d);
+size_t dp_iid_workspace_bytes(const dp_iid_problem *pb);
+/*   lam, prob [T][R]; V out: [T+1][S] (DP_STORE_V_ALL; slice t is V_t, slice T is 0) or
+ *   [S] (V_0 only); policy [T][R][S] int16 index into p_hat (ascending power) of the
+ *   chosen action at stage t (slice t-1), ties to the smallest next state, or NULL. */
+int dp_solve_iid(const dp_iid_problem *pb, const float *lam, const float *prob, float *V,
+                 int16_t *policy, void *ws, size_t ws_bytes, void *stream);
+
 /* Batched solves of many independent instances in one persistent launch.
  * A plan owns a device work table, its device workspace and a captured HIP graph; it
  * is created once for a fixed list of problems (host array probs[n]) and replayed with

@@ -52,20 +52,12 @@ def F(p: np.ndarray, eta: float) -> np.ndarray:
     return np.where(p >= 0, -p / eta, -eta * p)
 
 
-def algorithm1(s_hat, p_hat, lam, pi, eta: float):
-    """Return the expected value vectors V_hat [T+1, S] with V_hat[T] = 0.
-
-    lam, pi: [T, R] sampled levels and probabilities for stages t = 1..T.
-    """
+def precompute(s_hat, p_hat, eta: float):
+    """Algorithm 1's stage-invariant steps: next-state levels, proxies, indices, factors."""
     s_hat = np.asarray(s_hat, dtype=np.float64)
     p_hat = np.asarray(p_hat, dtype=np.float64)
-    lam = np.asarray(lam, dtype=np.float64)
-    pi = np.asarray(pi, dtype=np.float64)
-    T, R = lam.shape
-    S = s_hat.shape[0]
     delta = s_hat[1] - s_hat[0]
     s_bar = s_hat[-1]
-    V = np.zeros((T + 1, S))
     sigma = s_hat[:, None] + F(p_hat, eta)[None, :]                       # S x P
     z = np.clip(sigma, 0.0, s_bar) / delta
     z_lo = np.floor(z + 1e-9).astype(np.int64)
@@ -75,10 +67,45 @@ def algorithm1(s_hat, p_hat, lam, pi, eta: float):
     b = np.where(span > 0, (z - z_lo) / np.where(span > 0, span, 1.0), 0.0)
     tol = 1e-9 * s_bar
     infeasible = (sigma < -tol) | (sigma > s_bar + tol)
+    return z_lo, z_hi, b, infeasible
+
+
+def stage(pre, p_hat, lam_t, pi_t, V_t, rows=None):
+    """One iteration of the loop: returns (V_{t-1} [S or rows], Q_all [S|rows, P, R]).
+
+    ``rows`` restricts the computation to some SoC indices (memory only; every row is
+    computed independently of the others)."""
+    z_lo, z_hi, b, infeasible = pre
+    if rows is not None:
+        z_lo, z_hi, b, infeasible = z_lo[rows], z_hi[rows], b[rows], infeasible[rows]
+    V_t = np.asarray(V_t, dtype=np.float64)
+    Vn = (1.0 - b) * V_t[z_lo] + b * V_t[z_hi]                             # S x P
+    Vn = np.where(infeasible, -np.inf, Vn)
+    Q_all = np.outer(np.asarray(p_hat, np.float64),
+                     np.asarray(lam_t, np.float64))[None, :, :] + Vn[:, :, None]   # S x P x R
+    Q = Q_all.max(axis=1)                                                  # S x R
+    return Q @ np.asarray(pi_t, np.float64), Q_all
+
+
+def policy_index(Q_all):
+    """Maximising action per (s, r) with ties resolved to the largest index: the largest
+    power sold, i.e. the smallest next state (the convention of the grid-DP policy, where
+    a tie goes to the smallest next SoC)."""
+    P = Q_all.shape[1]
+    return P - 1 - np.argmax(Q_all[:, ::-1, :], axis=1)                   # S x R
+
+
+def algorithm1(s_hat, p_hat, lam, pi, eta: float):
+    """Return the expected value vectors V_hat [T+1, S] with V_hat[T] = 0.
+
+    lam, pi: [T, R] sampled levels and probabilities for stages t = 1..T.
+    """
+    lam = np.asarray(lam, dtype=np.float64)
+    pi = np.asarray(pi, dtype=np.float64)
+    T, R = lam.shape
+    S = np.asarray(s_hat).shape[0]
+    pre = precompute(s_hat, p_hat, eta)
+    V = np.zeros((T + 1, S))
     for t in range(T, 0, -1):
-        Vn = (1.0 - b) * V[t][z_lo] + b * V[t][z_hi]                       # S x P
-        Vn = np.where(infeasible, -np.inf, Vn)
-        Q_all = np.outer(p_hat, lam[t - 1])[None, :, :] + Vn[:, :, None]   # S x P x R
-        Q = Q_all.max(axis=1)                                              # S x R
-        V[t - 1] = Q @ pi[t - 1]
+        V[t - 1], _ = stage(pre, p_hat, lam[t - 1], pi[t - 1], V[t])
     return V

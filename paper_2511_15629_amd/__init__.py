@@ -18,7 +18,7 @@ from . import _lib
 from ._lib import DPError, DP_STORE_V_ALL, DP_VALIDATE, check, lib, make_problem
 
 __all__ = ["solve", "adjoint", "Solver", "DPFunction", "DPError", "set_sweep_shape",
-           "BatchPlan", "kernel_timing"]
+           "BatchPlan", "kernel_timing", "solve_independent", "power_grid_size"]
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -90,6 +90,48 @@ class Solver:
                              _ptr(self.V), _ptr(self.policy), _ptr(self.ckpt), _ptr(self.ws),
                              ctypes.c_size_t(self.ws.numel()), _stream(stream)))
         return self.V
+
+
+def _iid_problem(T, R, S, delta, eta, p_bar, store_all=False):
+    return _lib.IidProblem(int(T), int(R), int(S), 0, float(delta), float(eta), float(p_bar),
+                           DP_STORE_V_ALL if store_all else 0)
+
+
+def power_grid_size(S: int, delta: float, eta: float, p_bar: float):
+    """(P, n_c, n_d) of the paper's recombining power grid (host only)."""
+    pb = _iid_problem(1, 1, S, delta, eta, p_bar)
+    P, nc, nd = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    check(lib().dp_iid_action_grid(ctypes.byref(pb), ctypes.byref(P), ctypes.byref(nc),
+                                   ctypes.byref(nd)))
+    return P.value, nc.value, nd.value
+
+
+def solve_independent(lam: torch.Tensor, prob: torch.Tensor, S: int, delta: float, eta: float,
+                      p_bar: float, *, store_all: bool = False, policy: bool = False,
+                      stream=None):
+    """Stagewise-independent prices on the paper's power grid (Algorithm 1 as printed).
+
+    lam, prob [T, R] float32 device tensors (sampled levels and their probabilities).
+    Returns V ([T+1, S] expected values V_t if store_all, else V_0 [S]) and optionally the
+    int16 action index (ascending power grid) per stage, sample and SoC, [T, R, S].
+    """
+    lam = _dev_f32(lam, "lam")
+    prob = _dev_f32(prob, "prob")
+    T, R = lam.shape
+    if tuple(prob.shape) != (T, R):
+        raise ValueError("prob must have the shape of lam")
+    pb = _iid_problem(T, R, S, delta, eta, p_bar, store_all)
+    L = lib()
+    nws = L.dp_iid_workspace_bytes(ctypes.byref(pb))
+    if nws == 0:
+        check(_lib.DP_EINVAL)
+    dev = lam.device
+    V = torch.empty((T + 1, S) if store_all else (S,), dtype=torch.float32, device=dev)
+    pol = torch.empty((T, R, S), dtype=torch.int16, device=dev) if policy else None
+    ws = _workspace(nws, dev)
+    check(L.dp_solve_iid(ctypes.byref(pb), _ptr(lam), _ptr(prob), _ptr(V), _ptr(pol), _ptr(ws),
+                         ctypes.c_size_t(ws.numel()), _stream(stream)))
+    return {"V": V, "policy": pol, "_ws": ws}
 
 
 def solve(lam: torch.Tensor, P: torch.Tensor, storage, v_term: Optional[torch.Tensor] = None,

@@ -30,6 +30,7 @@ EXPORTS = (
     "dp_solve", "dp_adjoint_workspace_bytes", "dp_adjoint", "dp_batch_plan_create",
     "dp_batch_solve", "dp_batch_solve_looped", "dp_batch_plan_describe",
     "dp_batch_plan_destroy", "dp_set_sweep_shape", "dp_set_timing", "dp_get_timing",
+    "dp_iid_action_grid", "dp_iid_workspace_bytes", "dp_solve_iid",
 )
 
 
@@ -44,6 +45,12 @@ class Storage(ctypes.Structure):
                 ("reserved", ctypes.c_int32), ("delta", ctypes.c_float),
                 ("eta_c", ctypes.c_float), ("eta_d", ctypes.c_float),
                 ("c_deg", ctypes.c_float), ("c_start", ctypes.c_float)]
+
+
+class IidProblem(ctypes.Structure):
+    _fields_ = [("T", ctypes.c_int32), ("R", ctypes.c_int32), ("S", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("delta", ctypes.c_float), ("eta", ctypes.c_float),
+                ("p_bar", ctypes.c_float), ("flags", ctypes.c_uint32)]
 
 
 class Problem(ctypes.Structure):
@@ -81,6 +88,10 @@ def lib():
             "dp_batch_plan_destroy": ([p], None),
             "dp_set_sweep_shape": ([i, i, i, i], i),
             "dp_set_timing": ([i], i),
+            "dp_iid_action_grid": ([ctypes.POINTER(IidProblem), ctypes.POINTER(i),
+                                    ctypes.POINTER(i), ctypes.POINTER(i)], i),
+            "dp_iid_workspace_bytes": ([ctypes.POINTER(IidProblem)], sz),
+            "dp_solve_iid": ([ctypes.POINTER(IidProblem), p, p, p, p, p, sz, p], i),
             "dp_get_timing": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int),
                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)], i),
         }

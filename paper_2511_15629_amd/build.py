@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libdpgpu.so")
-SOURCES = ["dp_kernels.hip", "dp_api.hip", "dp_batch.hip"]
+SOURCES = ["dp_kernels.hip", "dp_api.hip", "dp_batch.hip", "dp_iid.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

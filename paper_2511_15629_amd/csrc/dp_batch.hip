@@ -30,6 +30,7 @@ namespace {
 const dpk::SweepShape kCandidates[] = {
     {8, 16, 8, 8}, {4, 16, 8, 8}, {8, 16, 4, 4}, {4, 16, 4, 4}, {8, 8, 4, 4}, {4, 8, 4, 2},
     {4, 16, 8, 4}, {8, 16, 4, 2}, {8, 8, 4, 1},  {4, 8, 4, 1},  {8, 16, 4, 1}, {4, 16, 4, 1},
+    {4, 4, 4, 1},  {8, 4, 4, 1},
 };
 
 struct TileClass {
@@ -72,8 +73,11 @@ struct dp_batch_plan {
     dpk::BatchDesc *ddesc = nullptr;
     dpk::BatchDesc *hstage = nullptr;      // pinned staging for descriptor updates
     std::vector<TileClass> classes;
-    dpk::ContractItem *d_citems = nullptr;
+    dpk::ContractItem *d_citems = nullptr;     // strip items (instances with K > 128)
     int n_citems = 0;
+    dpk::ContractItem *d_pitems = nullptr;     // panel items (instances with K <= 128)
+    int n_pitems = 0;
+    int panel_kmax = 0;
     char *ws = nullptr;
     size_t ws_bytes = 0;
     hipStream_t cap = nullptr;
@@ -93,6 +97,7 @@ static void destroy_plan(dp_batch_plan *p)
     for (auto &c : p->classes)
         if (c.d_items) (void)hipFree(c.d_items);
     if (p->d_citems) (void)hipFree(p->d_citems);
+    if (p->d_pitems) (void)hipFree(p->d_pitems);
     if (p->ddesc) (void)hipFree(p->ddesc);
     if (p->hstage) (void)hipHostFree(p->hstage);
     if (p->ws) (void)hipFree(p->ws);
@@ -107,8 +112,14 @@ static int enqueue_all(dp_batch_plan *p, hipStream_t s)
     hipError_t e = dpk::launch_batched_init(p->ddesc, p->n, s);
     if (e != hipSuccess) return hip_fail(e, "batched init");
     for (int tau = 1; tau <= p->Tmax; ++tau) {
-        e = dpk::launch_batched_contract(p->ddesc, p->d_citems, p->n_citems, tau, s);
-        if (e != hipSuccess) return hip_fail(e, "batched expectation");
+        if (p->n_pitems) {
+            e = dpk::launch_batched_panel(p->ddesc, p->d_pitems, p->n_pitems, tau, p->panel_kmax, s);
+            if (e != hipSuccess) return hip_fail(e, "batched expectation (panels)");
+        }
+        if (p->n_citems) {
+            e = dpk::launch_batched_contract(p->ddesc, p->d_citems, p->n_citems, tau, s);
+            if (e != hipSuccess) return hip_fail(e, "batched expectation (strips)");
+        }
         for (auto &c : p->classes) {
             if (c.items.empty()) continue;
             e = dpk::launch_batched_sweep(p->ddesc, c.d_items, (int)c.items.size(), tau, c.sh,
@@ -284,7 +295,7 @@ int dp_batch_plan_create(dp_batch_plan **out, int n, const dp_problem *probs,
     p->ws_bytes = total;
     const float *zeros_lam = reinterpret_cast<const float *>(p->ws + zoff);
     p->hdesc.resize(n);
-    std::vector<dpk::ContractItem> citems;
+    std::vector<dpk::ContractItem> citems, pitems;
     for (int i = 0; i < n; ++i) {
         const dp_problem &pb = p->probs[i];
         const SolveLayout L = solve_layout(&pb);
@@ -305,15 +316,32 @@ int dp_batch_plan_create(dp_batch_plan **out, int n, const dp_problem *probs,
         d.vbuf1 = reinterpret_cast<float *>(base + L.vB);
         d.W = reinterpret_cast<float *>(base + L.W);
         d.off = reinterpret_cast<double *>(base + L.off);
+        // K <= 128: one item = a 64-column panel over every row tile (P_t in LDS);
+        // otherwise one item = a strip of four adjacent 16 x 16 tiles of one row tile
         const int ntm = (pb.K + 15) / 16, ntn = (pb.st.S + 15) / 16;
-        for (int tn = 0; tn < ntn; ++tn)
-            for (int tm = 0; tm < ntm; ++tm) citems.push_back({i, tm, tn});
+        if (pb.K <= 128) {
+            for (int tn = 0; tn < ntn; tn += 4) pitems.push_back({i, 0, tn});
+            p->panel_kmax = std::max(p->panel_kmax, pb.K);
+        } else {
+            for (int tn = 0; tn < ntn; tn += 4)
+                for (int tm = 0; tm < ntm; ++tm) citems.push_back({i, tm, tn});
+        }
     }
     p->n_citems = (int)citems.size();
-    e = hipMalloc(&p->d_citems, sizeof(dpk::ContractItem) * citems.size());
-    if (e == hipSuccess)
-        e = hipMemcpy(p->d_citems, citems.data(), sizeof(dpk::ContractItem) * citems.size(),
-                      hipMemcpyHostToDevice);
+    p->n_pitems = (int)pitems.size();
+    e = hipSuccess;
+    if (!citems.empty()) {
+        e = hipMalloc(&p->d_citems, sizeof(dpk::ContractItem) * citems.size());
+        if (e == hipSuccess)
+            e = hipMemcpy(p->d_citems, citems.data(), sizeof(dpk::ContractItem) * citems.size(),
+                          hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess && !pitems.empty()) {
+        e = hipMalloc(&p->d_pitems, sizeof(dpk::ContractItem) * pitems.size());
+        if (e == hipSuccess)
+            e = hipMemcpy(p->d_pitems, pitems.data(), sizeof(dpk::ContractItem) * pitems.size(),
+                          hipMemcpyHostToDevice);
+    }
     if (e != hipSuccess) {
         destroy_plan(p);
         return hip_fail(e, "expectation item table");
@@ -393,8 +421,8 @@ int dp_batch_plan_create(dp_batch_plan **out, int n, const dp_problem *probs,
     }
     // description
     char buf[512];
-    snprintf(buf, sizeof buf, "dp_batch_plan: %d instances, %d batch stages, %d expectation tiles, %zu bytes workspace\n",
-             n, p->Tmax, p->n_citems, p->ws_bytes);
+    snprintf(buf, sizeof buf, "dp_batch_plan: %d instances, %d batch stages, %d expectation panels + %d strips, %zu bytes workspace\n",
+             n, p->Tmax, p->n_pitems, p->n_citems, p->ws_bytes);
     p->text = buf;
     for (auto &c : p->classes) {
         snprintf(buf, sizeof buf, "  class span %d..%d: shape R=%d D=%d NW=%d NSPLIT=%d, %zu instances, %zu blocks/stage, %zu B LDS%s\n",

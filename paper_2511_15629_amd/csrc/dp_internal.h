@@ -54,8 +54,40 @@ struct ContractItem {
 hipError_t launch_batched_init(const BatchDesc *desc, int n, hipStream_t stream);
 hipError_t launch_batched_contract(const BatchDesc *desc, const ContractItem *items, int n,
                                    int tau, hipStream_t stream);
+// Column-panel expectation for K <= 128 (one block per 64-column panel).
+hipError_t launch_batched_panel(const BatchDesc *desc, const ContractItem *items, int n, int tau,
+                                int kmax, hipStream_t stream);
 hipError_t launch_batched_sweep(const BatchDesc *desc, const SweepItem *items, int n, int tau,
                                 const SweepShape &sh, size_t lds, hipStream_t stream);
+
+// Stagewise-independent prices on the paper's power grid (Algorithm 1 as printed):
+// R price samples per stage, interior actions = whole SoC steps [-w_down, w_up], plus the
+// two endpoint actions -p_bar (charge) and +p_bar (discharge) whose next states are
+// interpolated between two grid points.
+struct IidEnd {              // per SoC index s, one endpoint action
+    int lo, hi;              // next-state indices (lo = -1: infeasible)
+    float b;                 // interpolation factor
+};
+struct IidArgs {
+    const float *Vin;        // normalised V_t [S]
+    float *Vout;             // normalised V_{t-1} [S]
+    const float *lam;        // lam_t [R]
+    const float *prob;       // pi_t [R]
+    const IidEnd *endc;      // charge endpoint table [S]
+    const IidEnd *endd;      // discharge endpoint table [S]
+    int R, S, w_up, w_down, P;
+    Payoff pay;              // interior payoff (delta, eta_c = eta_d = eta, costs)
+    float p_bar;
+    const double *off_next;  // C_t (offset of Vin)
+    double *off_cur;         // C_{t-1}
+    float *vabs;             // [S] absolute V_{t-1} (nullable)
+    int16_t *pol;            // [R][S] action index into the ascending power grid (nullable)
+};
+hipError_t launch_iid_stage(const IidArgs &a, hipStream_t stream);
+size_t iid_lds_bytes(int R, int S, int w_up, int w_down);
+hipError_t launch_iid_tables(int S, double delta, double eta, double p_bar, IidEnd *endc,
+                             IidEnd *endd, hipStream_t stream);
+hipError_t launch_iid_init(float *V, int S, double *off, float *vabs, hipStream_t stream);
 
 // Stage kernels (launchers; all asynchronous on `stream`).
 hipError_t launch_contract(const float *A, bool transA, const float *B, int ldb, float *C,

@@ -84,6 +84,62 @@ __device__ __forceinline__ void contract_tile(const float *__restrict__ A,
     }
 }
 
+// Strip of NT adjacent 16 x 16 tiles (16 rows x 16 NT columns) per wave: each step loads
+// one A operand and NT B operands and issues NT MFMAs, so A loads and per-wave setup are
+// shared by NT tiles.  Each tile's MFMA chain (operands, order) is exactly that of
+// contract_tile, so the results are bitwise the same.
+template <int CH, int NT>
+__device__ __forceinline__ void contract_strip(const float *__restrict__ A,
+                                               const float *__restrict__ B, int ldb,
+                                               float *__restrict__ C, int ldc, int K, int N,
+                                               int tm, int tn0)
+{
+    const int lane = threadIdx.x & 63;
+    const int arow = tm * 16 + (lane & 15);
+    const int kq = lane >> 4;
+    const bool rok = arow < K;
+    int col[NT];
+    bool cok[NT];
+#pragma unroll
+    for (int n = 0; n < NT; ++n) {
+        col[n] = (tn0 + n) * 16 + (lane & 15);
+        cok[n] = col[n] < N;
+    }
+    floatx4 acc[NT];
+#pragma unroll
+    for (int n = 0; n < NT; ++n) acc[n] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 4 * CH) {
+        float av[CH], bv[CH][NT];
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+            const int kx = k0 + 4 * i + kq;
+            const bool kok = kx < K;
+            av[i] = (kok && rok) ? A[(size_t)arow * K + kx] : 0.f;
+#pragma unroll
+            for (int n = 0; n < NT; ++n)
+                bv[i][n] = (kok && cok[n]) ? B[(size_t)kx * ldb + col[n]] : 0.f;
+        }
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+            if (k0 + 4 * i < K) {
+#pragma unroll
+                for (int n = 0; n < NT; ++n)
+                    acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[i][n], acc[n], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int n = 0; n < NT; ++n) {
+        if (cok[n]) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = tm * 16 + 4 * kq + v;
+                if (r < K) C[(size_t)r * ldc + col[n]] = acc[n][v];
+            }
+        }
+    }
+}
+
 template <bool TRANS_A>
 __global__ __launch_bounds__(256) void contract_kernel(const float *__restrict__ A,
                                                        const float *__restrict__ B, int ldb,
@@ -279,7 +335,9 @@ size_t sweep_lds_bytes(const SweepShape &sh, int w_up, int w_down)
     X(8, 8, 4, 1)          \
     X(4, 8, 4, 1)          \
     X(8, 16, 4, 1)         \
-    X(4, 16, 4, 1)
+    X(4, 16, 4, 1)         \
+    X(4, 4, 4, 1)          \
+    X(8, 4, 4, 1)
 
 bool sweep_shape_supported(const SweepShape &sh)
 {
@@ -304,6 +362,213 @@ hipError_t launch_sweep(const SweepArgs &a, const SweepShape &sh, hipStream_t st
     DP_SWEEP_SHAPES(X)
 #undef X
     return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------------------------------
+// Stagewise-independent prices on the paper's power grid (Sec. III, Algorithm 1).
+//
+// One launch per stage.  Block = a tile of TS SoC indices for all R price samples; the
+// value row V_t over every next state the tile can reach is staged in LDS once and shared
+// by the R samples (in this model the continuation value does not depend on the sample).
+// Work unit = (sample r, group of G consecutive outputs): the interior moves (whole grid
+// steps, Algorithm 1's non-interpolated columns) run through the chunked max-plus loop
+// with the exact first-argmax rescan; the two endpoint actions +-p_bar (interpolated
+// columns) are then compared in next-state order (discharge endpoint first, charge
+// endpoint last, strict >), giving the smallest maximising next state.  Q(s, r) goes to
+// LDS and V_{t-1}(s) = sum_r pi_r Q(s, r) is summed in ascending r (the expectation).
+// ------------------------------------------------------------------------------------
+constexpr int IID_THREADS = 512;
+constexpr int IID_D = 8;
+constexpr int IID_G = 4;             // outputs per unit
+constexpr int IID_TS = 32;           // outputs per block
+
+// Endpoint tables in FP64 with the formulas of Algorithm 1: sigma = s delta + F(p),
+// z = clip(sigma, 0, s_bar) / delta, z- = floor(z + 1e-9), z+ = ceil(z - 1e-9),
+// b = (z - z-) / (z+ - z-) (0 when equal), infeasible when sigma < -tol or
+// sigma > s_bar + tol, tol = 1e-9 s_bar.
+__global__ void iid_tables_kernel(int S, double delta, double eta, double p_bar, IidEnd *endc,
+                                  IidEnd *endd)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    const double s_bar = (double)(S - 1) * delta;
+    const double tol = 1e-9 * s_bar;
+    for (int side = 0; side < 2; ++side) {
+        // charge endpoint p = -p_bar: F = -eta p = eta p_bar; discharge p = +p_bar: F = -p / eta
+        const double F = side == 0 ? eta * p_bar : -(p_bar / eta);
+        const double sigma = (double)s * delta + F;
+        IidEnd e;
+        if (sigma < -tol || sigma > s_bar + tol) {
+            e.lo = -1;
+            e.hi = -1;
+            e.b = 0.0f;
+        } else {
+            const double z = fmin(fmax(sigma, 0.0), s_bar) / delta;
+            int lo = (int)floor(z + 1e-9), hi = (int)ceil(z - 1e-9);
+            lo = min(lo, hi);
+            e.lo = lo;
+            e.hi = hi;
+            e.b = hi > lo ? (float)((z - lo) / (double)(hi - lo)) : 0.0f;
+        }
+        (side == 0 ? endc : endd)[s] = e;
+    }
+}
+
+hipError_t launch_iid_tables(int S, double delta, double eta, double p_bar, IidEnd *endc,
+                             IidEnd *endd, hipStream_t stream)
+{
+    hipLaunchKernelGGL(iid_tables_kernel, dim3((S + 255) / 256), dim3(256), 0, stream, S, delta,
+                       eta, p_bar, endc, endd);
+    return hipGetLastError();
+}
+
+__global__ void iid_init_kernel(float *V, int S, double *off, float *vabs)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < S; i += gridDim.x * blockDim.x) {
+        V[i] = 0.0f;
+        if (vabs) vabs[i] = 0.0f;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) off[0] = 0.0;
+}
+
+hipError_t launch_iid_init(float *V, int S, double *off, float *vabs, hipStream_t stream)
+{
+    hipLaunchKernelGGL(iid_init_kernel, dim3((S + 255) / 256), dim3(256), 0, stream, V, S, off,
+                       vabs);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(IID_THREADS) void iid_stage_kernel(IidArgs a)
+{
+    constexpr int D = IID_D, G = IID_G, TS = IID_TS;
+    extern __shared__ float4 smem4[];
+    float *smem = reinterpret_cast<float *>(smem4);
+    const int tid = threadIdx.x;
+    const int S = a.S, R = a.R;
+    const int s0 = blockIdx.x * TS;
+    const int s_end = min(s0 + TS, S);
+    const int dlo = max(-a.w_down, -(s_end - 1));
+    const int dhi = min(a.w_up, S - 1 - s0);
+    const int nchunk = (dhi - dlo + 1 + D - 1) / D;
+    const int nrl = nchunk * D;
+    // LDS: value halo over j in [s0 - w_down - 1, s0 + TS + w_up + 1] (-inf outside [0, S)),
+    // reward tables over the tile's interior moves, Q[R][TS].
+    const int hb = s0 - a.w_down - 1;                      // first halo index
+    const int nh = (TS + a.w_down + a.w_up + 3 + D + 3) & ~3;
+    float *Vh = smem;
+    float *gl = Vh + nh;
+    float *hl = gl + nrl;
+    float *Q = hl + nrl;                                   // [R][TS]
+    const float NEG = -INFINITY;
+    for (int i = tid; i < nh; i += IID_THREADS) {
+        const int j = hb + i;
+        Vh[i] = (j >= 0 && j < S) ? a.Vin[j] : NEG;
+    }
+    for (int i = tid; i < nrl; i += IID_THREADS) {
+        const int d = dlo + i;
+        gl[i] = move_energy(d, a.pay);
+        hl[i] = (d <= dhi) ? move_cost(d, a.pay) : NEG;
+    }
+    __syncthreads();
+    const int ngrp = TS / G;
+    const int units = R * ngrp;
+    const int woff = s0 + dlo - hb;                        // halo index of the tile's first next state
+    for (int u = tid; u < units; u += IID_THREADS) {
+        const int r = u / ngrp, grp = u - r * ngrp;
+        const int o0 = grp * G;                            // first output of the group (local)
+        const float lam = a.lam[r];
+        const float *Wl = Vh + woff + o0;
+        float best[G];
+        int cid[G];
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            best[i] = NEG;
+            cid[i] = 0;
+        }
+        for (int c = 0; c < nchunk; ++c) {
+            float w[G + D];
+#pragma unroll
+            for (int m = 0; m < G + D - 1; ++m) w[m] = Wl[c * D + m];
+            float rr[D];
+#pragma unroll
+            for (int d = 0; d < D; ++d) rr[d] = fmaf(lam, gl[c * D + d], hl[c * D + d]);
+#pragma unroll
+            for (int i = 0; i < G; ++i) {
+                float m = best[i];
+#pragma unroll
+                for (int d = 0; d < D; ++d) m = fmaxf(m, w[i + d] + rr[d]);
+                cid[i] = (m > best[i]) ? c : cid[i];
+                best[i] = m;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            const int s = s0 + o0 + i;
+            if (s >= S) continue;
+            // first interior move attaining the maximum
+            int arg = 0;
+            for (int d = D - 1; d >= 0; --d) {
+                const float x = Wl[cid[i] * D + i + d] + fmaf(lam, gl[cid[i] * D + d], hl[cid[i] * D + d]);
+                if (x == best[i]) arg = d;
+            }
+            const int dstar = dlo + cid[i] * D + arg;      // interior move (next state s + dstar)
+            float q = best[i];
+            int act = a.w_up + 1 - dstar;                  // ascending-power index of that move
+            // discharge endpoint: smallest next state, wins ties
+            const IidEnd ed = a.endd[s];
+            if (ed.lo >= 0) {
+                const float vl = Vh[ed.lo - hb], vh = Vh[ed.hi - hb];
+                const float x = fmaf(lam, a.p_bar, (1.0f - ed.b) * vl + ed.b * vh);
+                if (x >= q) {
+                    q = x;
+                    act = a.P - 1;
+                }
+            }
+            // charge endpoint: largest next state, loses ties
+            const IidEnd ec = a.endc[s];
+            if (ec.lo >= 0) {
+                const float vl = Vh[ec.lo - hb], vh = Vh[ec.hi - hb];
+                const float x = fmaf(lam, -a.p_bar, (1.0f - ec.b) * vl + ec.b * vh);
+                if (x > q) {
+                    q = x;
+                    act = 0;
+                }
+            }
+            Q[r * TS + o0 + i] = q;
+            if (a.pol) a.pol[(size_t)r * S + s] = (int16_t)act;
+        }
+    }
+    __syncthreads();
+    const float shift = a.Vin[0];
+    const double Ct = a.off_next[0] + (double)shift;
+    for (int o = tid; o < TS; o += IID_THREADS) {
+        const int s = s0 + o;
+        if (s >= S) continue;
+        float acc = 0.0f;
+        for (int r = 0; r < R; ++r) acc = fmaf(a.prob[r], Q[r * TS + o], acc);
+        const float vn = acc - shift;
+        a.Vout[s] = vn;
+        if (a.vabs) a.vabs[s] = (float)((double)vn + Ct);
+    }
+    if (blockIdx.x == 0 && tid == 0) a.off_cur[0] = Ct;
+}
+
+size_t iid_lds_bytes(int R, int S, int w_up, int w_down)
+{
+    (void)S;
+    const int span = w_up + w_down + 1;
+    const int nrl = ((span + IID_D - 1) / IID_D) * IID_D;
+    const int nh = (IID_TS + w_down + w_up + 3 + IID_D + 3) & ~3;
+    return sizeof(float) * ((size_t)nh + 2 * (size_t)nrl + (size_t)R * IID_TS);
+}
+
+hipError_t launch_iid_stage(const IidArgs &a, hipStream_t stream)
+{
+    const size_t lds = iid_lds_bytes(a.R, a.S, a.w_up, a.w_down);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(iid_stage_kernel, dim3((a.S + IID_TS - 1) / IID_TS), dim3(IID_THREADS), lds,
+                       stream, a);
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------------------------------
@@ -352,8 +617,73 @@ __global__ __launch_bounds__(256) void batched_contract_kernel(const BatchDesc *
     const int t = d.T - tau + 1;
     if (t < 1) return;
     const float *vin = ((d.T - t) & 1) ? d.vbuf1 : d.vbuf0;
-    contract_tile<false, 8>(d.P + (size_t)(t - 1) * d.K * d.K, vin, d.ld, d.W, d.ld, d.K, d.S,
-                            it.tm, it.tn);
+    contract_strip<8, 4>(d.P + (size_t)(t - 1) * d.K * d.K, vin, d.ld, d.W, d.ld, d.K, d.S,
+                         it.tm, it.tn);
+}
+
+// Column-panel expectation for K <= 128: block = 64 columns (one 16-column tile per wave)
+// x every row tile.  P_t is staged once per block in LDS (row stride K + 1 against bank
+// conflicts); each wave keeps its B column operands in registers and walks the row tiles,
+// so V_{t+1} is read once per stage.  Every tile's MFMA chain equals contract_tile's.
+constexpr int PANEL_KMAX = 128;
+
+__global__ __launch_bounds__(256) void batched_panel_kernel(const BatchDesc *__restrict__ desc,
+                                                            const ContractItem *__restrict__ items,
+                                                            int tau)
+{
+    extern __shared__ float4 smem4[];
+    float *Pl = reinterpret_cast<float *>(smem4);
+    const ContractItem it = items[blockIdx.x];
+    const BatchDesc d = desc[it.inst];
+    const int t = d.T - tau + 1;
+    if (t < 1) return;
+    const int K = d.K, S = d.S, ldp = K + 1;
+    const float *P = d.P + (size_t)(t - 1) * K * K;
+    for (int e = threadIdx.x; e < K * K; e += 256) {
+        const int r = e / K, c = e - r * K;
+        Pl[r * ldp + c] = P[e];
+    }
+    const float *B = ((d.T - t) & 1) ? d.vbuf1 : d.vbuf0;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int kq = lane >> 4;
+    const int col = (it.tn + wave) * 16 + (lane & 15);
+    const bool cok = col < S;
+    float bv[PANEL_KMAX / 4];
+#pragma unroll
+    for (int i = 0; i < PANEL_KMAX / 4; ++i) {
+        const int kx = 4 * i + kq;
+        bv[i] = (kx < K && cok) ? B[(size_t)kx * d.ld + col] : 0.f;
+    }
+    __syncthreads();
+    const int ntm = (K + 15) >> 4;
+    for (int tm = 0; tm < ntm; ++tm) {
+        const int arow = tm * 16 + (lane & 15);
+        const bool rok = arow < K;
+        floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int i = 0; i < PANEL_KMAX / 4; ++i) {
+            if (4 * i < K) {
+                const int kx = 4 * i + kq;
+                const float av = (kx < K && rok) ? Pl[arow * ldp + kx] : 0.f;
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[i], acc, 0, 0, 0);
+            }
+        }
+        if (cok) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = tm * 16 + 4 * kq + v;
+                if (r < K) d.W[(size_t)r * d.ld + col] = acc[v];
+            }
+        }
+    }
+}
+
+hipError_t launch_batched_panel(const BatchDesc *desc, const ContractItem *items, int n, int tau,
+                                int kmax, hipStream_t stream)
+{
+    const size_t lds = sizeof(float) * (size_t)kmax * (kmax + 1);
+    hipLaunchKernelGGL(batched_panel_kernel, dim3(n), dim3(256), lds, stream, desc, items, tau);
+    return hipGetLastError();
 }
 
 __global__ void batched_init_kernel(const BatchDesc *__restrict__ desc)

@@ -267,6 +267,53 @@ def default_seed(K: int, S: int, s0: int = 0) -> np.ndarray:
     return om
 
 
+# ----------------------------------------------------------------------------------
+# Stagewise-independent workload shaped like Table 3 (8784 hours, 200 samples per hour)
+# ----------------------------------------------------------------------------------
+
+TABLE3 = [(4, 0.1), (20, 0.1), (100, 0.1), (4, 0.01), (20, 0.01), (100, 0.01)]   # (hours, delta)
+
+
+@dataclasses.dataclass
+class IidInstance:
+    """Stagewise-independent prices: lam [T, R] levels, prob [T, R] probabilities."""
+
+    name: str
+    T: int
+    R: int
+    S: int
+    delta: float
+    eta: float
+    p_bar: float
+    lam: np.ndarray
+    prob: np.ndarray
+
+
+def iid_prices(T: int, R: int, *, seed: int, scale: float = 12.0, dof: float = 3.0):
+    """Synthetic hourly day-ahead curve plus R equal-mass quantiles of a heavy-tailed
+    real-time spread (Student t), the shape of the quantile forecasts of Sec. IV."""
+    from scipy.stats import t as student_t
+    rng = np.random.Generator(np.random.PCG64(seed))
+    h = np.arange(T) % 24
+    d = np.arange(T) // 24
+    da = 45.0 + 15.0 * np.sin(2 * np.pi * (h - 8) / 24.0) + 10.0 * np.sin(2 * np.pi * d / 366.0)
+    da = da + rng.normal(0.0, 5.0, T)
+    q = student_t.ppf((np.arange(R) + 0.5) / R, dof)
+    spread = scale * (1.0 + 0.3 * np.sin(2 * np.pi * h / 24.0))[:, None] * q[None, :]
+    lam = f32(da[:, None] + spread)
+    prob = quantize_rows(np.full((T, R), 1.0 / R))
+    return lam, prob
+
+
+def table3_instance(hours: float, delta: float, *, T: int = 8784, R: int = 200, seed: int = 6):
+    """1 MW battery of the given duration on grid step delta, eta = sqrt(0.85) (Sec. V)."""
+    S = int(round(hours / delta)) + 1
+    lam, prob = iid_prices(T, R, seed=seed)
+    eta = float(np.float32(math.sqrt(0.85)))
+    return IidInstance(f"iid_T{T}_R{R}_S{S}_d{delta}", T, R, S, float(np.float32(delta)), eta,
+                       1.0, lam, prob)
+
+
 WORKLOADS = {
     "day_hourly_small": day_hourly_small,
     "day_5min": day_5min,
