@@ -190,6 +190,39 @@ def batch_compare(dp, torch, reps=2):
     return out
 
 
+# Full-year solve times of the stagewise-independent variant on the power grid as the paper
+# reports them (Table 3: 8784 hourly stages, 200 samples; NumPy on a 32-core Xeon, CuPy on an
+# L40S).  Context for the same workload shapes here, not a target of the headline metric.
+TABLE3_PAPER_S = {(4, 0.1): (3.98, 2.77), (20, 0.1): (18.29, 2.81), (100, 0.1): (98.12, 2.94),
+                  (4, 0.01): (397.80, 4.88), (20, 0.01): (1996.02, 19.17),
+                  (100, 0.01): (9972.64, 86.67)}
+
+
+def table3_independent(dp, torch):
+    """One full-year value solve per Table 3 row (V_0 only, as Algorithm 1 returns)."""
+    import workloads as wl
+    rows = []
+    for hours, delta in wl.TABLE3:
+        inst = wl.table3_instance(hours, delta)
+        lam = torch.from_numpy(inst.lam).cuda()
+        prob = torch.from_numpy(inst.prob).cuda()
+        P = dp.power_grid_size(inst.S, inst.delta, inst.eta, inst.p_bar)[0]
+        dp.solve_independent(lam[:8], prob[:8], inst.S, inst.delta, inst.eta, inst.p_bar)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dp.solve_independent(lam, prob, inst.S, inst.delta, inst.eta, inst.p_bar)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        cpu_s, gpu_s = TABLE3_PAPER_S[(hours, delta)]
+        rows.append({"hours": hours, "S": inst.S, "P": P, "T": inst.T, "R": inst.R,
+                     "s": round(dt, 4),
+                     "sample_action_pairs_per_s": round(inst.S * P * inst.R * inst.T / dt, 1),
+                     "paper_gpu_s": gpu_s, "paper_cpu_s": cpu_s,
+                     "paper_gpu_over_this": round(gpu_s / dt, 1)})
+        del lam, prob
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -247,6 +280,7 @@ def main():
         del year
         extra["adjoint_vs_value"] = adjoint_ratio(dp, torch, wl.day_5min_adjoint())
         extra["batched_vs_looped"] = batch_compare(dp, torch)
+        extra["table3_independent"] = table3_independent(dp, torch)
         line["extra"] = extra
     print(json.dumps(line), flush=True)
 

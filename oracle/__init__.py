@@ -17,6 +17,9 @@ Contents
   stagewise-independent model (power-action grid, interpolation, -inf mask, max, mean).
 * ``hull`` -- the concave envelope of a finite point set by its definition (max over
   pairs), used to check the host bid-curve convexifier (Eq. (9)-(10)).
+* ``arbitrage`` -- the continuous deterministic problem of Eq. (1)-(2) as the MILP of
+  Eq. (3a)-(3d), its LP relaxation, the LP restriction of Sec. V-B and the plain LP
+  (SciPy HiGHS, sparse), for the accuracy studies of Sec. V.
 """
 from __future__ import annotations
 

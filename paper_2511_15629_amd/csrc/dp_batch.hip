@@ -30,7 +30,8 @@ namespace {
 const dpk::SweepShape kCandidates[] = {
     {8, 16, 8, 8}, {4, 16, 8, 8}, {8, 16, 4, 4}, {4, 16, 4, 4}, {8, 8, 4, 4}, {4, 8, 4, 2},
     {4, 16, 8, 4}, {8, 16, 4, 2}, {8, 8, 4, 1},  {4, 8, 4, 1},  {8, 16, 4, 1}, {4, 16, 4, 1},
-    {4, 4, 4, 1},  {8, 4, 4, 1},
+    {4, 4, 4, 1},  {8, 4, 4, 1},  {4, 8, 2, 1},  {4, 4, 2, 1},  {4, 8, 1, 1},  {8, 8, 1, 1},
+    {4, 4, 1, 1},
 };
 
 struct TileClass {
@@ -75,9 +76,9 @@ struct dp_batch_plan {
     std::vector<TileClass> classes;
     dpk::ContractItem *d_citems = nullptr;     // strip items (instances with K > 128)
     int n_citems = 0;
-    dpk::ContractItem *d_pitems = nullptr;     // panel items (instances with K <= 128)
-    int n_pitems = 0;
-    int panel_kmax = 0;
+    dpk::ContractItem *d_pitems = nullptr;     // panel items (instances with K <= 128),
+    int n_pitems = 0;                          // grouped by dpk::panel_class
+    int pan_off[3] = {0, 0, 0}, pan_n[3] = {0, 0, 0}, pan_kmax[3] = {0, 0, 0};
     char *ws = nullptr;
     size_t ws_bytes = 0;
     hipStream_t cap = nullptr;
@@ -112,8 +113,10 @@ static int enqueue_all(dp_batch_plan *p, hipStream_t s)
     hipError_t e = dpk::launch_batched_init(p->ddesc, p->n, s);
     if (e != hipSuccess) return hip_fail(e, "batched init");
     for (int tau = 1; tau <= p->Tmax; ++tau) {
-        if (p->n_pitems) {
-            e = dpk::launch_batched_panel(p->ddesc, p->d_pitems, p->n_pitems, tau, p->panel_kmax, s);
+        for (int c = 0; c < 3; ++c) {
+            if (!p->pan_n[c]) continue;
+            e = dpk::launch_batched_panel(p->ddesc, p->d_pitems + p->pan_off[c], p->pan_n[c], tau,
+                                          p->pan_kmax[c], s);
             if (e != hipSuccess) return hip_fail(e, "batched expectation (panels)");
         }
         if (p->n_citems) {
@@ -295,7 +298,7 @@ int dp_batch_plan_create(dp_batch_plan **out, int n, const dp_problem *probs,
     p->ws_bytes = total;
     const float *zeros_lam = reinterpret_cast<const float *>(p->ws + zoff);
     p->hdesc.resize(n);
-    std::vector<dpk::ContractItem> citems, pitems;
+    std::vector<dpk::ContractItem> citems, pclass[3];
     for (int i = 0; i < n; ++i) {
         const dp_problem &pb = p->probs[i];
         const SolveLayout L = solve_layout(&pb);
@@ -316,18 +319,27 @@ int dp_batch_plan_create(dp_batch_plan **out, int n, const dp_problem *probs,
         d.vbuf1 = reinterpret_cast<float *>(base + L.vB);
         d.W = reinterpret_cast<float *>(base + L.W);
         d.off = reinterpret_cast<double *>(base + L.off);
-        // K <= 128: one item = a 64-column panel over every row tile (P_t in LDS);
-        // otherwise one item = a strip of four adjacent 16 x 16 tiles of one row tile
+        // K <= 128: one item = up to four 64-column panels over every row tile (P_t in
+        // LDS); otherwise one item = a strip of four adjacent 16 x 16 tiles of one row tile
         const int ntm = (pb.K + 15) / 16, ntn = (pb.st.S + 15) / 16;
         if (pb.K <= 128) {
-            for (int tn = 0; tn < ntn; tn += 4) pitems.push_back({i, 0, tn});
-            p->panel_kmax = std::max(p->panel_kmax, pb.K);
+            // items of up to four panels (P_t staged once per item)
+            const int c = dpk::panel_class(pb.K);
+            for (int tn = 0; tn < ntn; tn += 16)
+                pclass[c].push_back({i, std::min(4, (ntn - tn + 3) / 4), tn});
+            p->pan_kmax[c] = std::max(p->pan_kmax[c], pb.K);
         } else {
             for (int tn = 0; tn < ntn; tn += 4)
                 for (int tm = 0; tm < ntm; ++tm) citems.push_back({i, tm, tn});
         }
     }
     p->n_citems = (int)citems.size();
+    std::vector<dpk::ContractItem> pitems;
+    for (int c = 0; c < 3; ++c) {
+        p->pan_off[c] = (int)pitems.size();
+        p->pan_n[c] = (int)pclass[c].size();
+        pitems.insert(pitems.end(), pclass[c].begin(), pclass[c].end());
+    }
     p->n_pitems = (int)pitems.size();
     e = hipSuccess;
     if (!citems.empty()) {

@@ -48,13 +48,17 @@ struct SweepItem {
     int inst, k, tile;
 };
 struct ContractItem {
-    int inst, tm, tn;
+    int inst, tm, tn;      // strips: row tile, first column tile; panels: panel count, first column tile
 };
 
 hipError_t launch_batched_init(const BatchDesc *desc, int n, hipStream_t stream);
 hipError_t launch_batched_contract(const BatchDesc *desc, const ContractItem *items, int n,
                                    int tau, hipStream_t stream);
-// Column-panel expectation for K <= 128 (one block per 64-column panel).
+// Column-panel expectation for K <= 128 (one block per item of up to four 64-column
+// panels; ContractItem.tm = panel count, .tn = first 16-column tile).  One launch covers
+// the items of one class panel_class(K) (K <= 32, <= 64, <= 128); kmax = the largest K
+// among them.
+int panel_class(int K);
 hipError_t launch_batched_panel(const BatchDesc *desc, const ContractItem *items, int n, int tau,
                                 int kmax, hipStream_t stream);
 hipError_t launch_batched_sweep(const BatchDesc *desc, const SweepItem *items, int n, int tau,

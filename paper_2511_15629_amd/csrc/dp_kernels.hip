@@ -337,7 +337,12 @@ size_t sweep_lds_bytes(const SweepShape &sh, int w_up, int w_down)
     X(8, 16, 4, 1)         \
     X(4, 16, 4, 1)         \
     X(4, 4, 4, 1)          \
-    X(8, 4, 4, 1)
+    X(8, 4, 4, 1)          \
+    X(4, 8, 2, 1)          \
+    X(4, 4, 2, 1)          \
+    X(4, 8, 1, 1)          \
+    X(8, 8, 1, 1)          \
+    X(4, 4, 1, 1)
 
 bool sweep_shape_supported(const SweepShape &sh)
 {
@@ -621,12 +626,96 @@ __global__ __launch_bounds__(256) void batched_contract_kernel(const BatchDesc *
                          it.tm, it.tn);
 }
 
-// Column-panel expectation for K <= 128: block = 64 columns (one 16-column tile per wave)
-// x every row tile.  P_t is staged once per block in LDS (row stride K + 1 against bank
-// conflicts); each wave keeps its B column operands in registers and walks the row tiles,
-// so V_{t+1} is read once per stage.  Every tile's MFMA chain equals contract_tile's.
+// Column-panel expectation for K <= 128.  An item is `tm` consecutive 64-column panels of
+// one instance (field reuse: tm = panel count, tn = first 16-column tile); each wave of the
+// block owns one 16-column tile of a panel and walks every row tile.  P_t is staged once
+// per item in LDS with a row stride of panel_ld(K) = 4 (mod 32) words, so the 16 rows x 4
+// k-offsets a wave reads at once fall in distinct banks; when K % 4 != 0 the columns
+// K .. 4 ceil(K/4) - 1 are zero.  The B operands of the next panel are loaded while the
+// current panel's MFMAs run (for K <= 64; beyond, the registers would cost occupancy).
+// The tile loop is instantiated per k-step count NK = ceil(K/4):
+// all NK A operands of a tile are read from LDS ahead of a straight-line chain of NK MFMAs.
+// Rows beyond K read row K-1 (their outputs are discarded).  Every tile's chain is exactly
+// contract_tile's (NK MFMAs in k order on the same operands), so the results are bitwise
+// the same.
 constexpr int PANEL_KMAX = 128;
 
+__host__ __device__ constexpr int panel_ld(int K) { return ((K + 31) / 32) * 32 + 4; }
+
+template <int NK>
+__device__ __forceinline__ void panel_load_b(const float *__restrict__ B, int ldb, int K,
+                                             int col, bool cok, float (&bv)[NK])
+{
+    const int kq = (threadIdx.x & 63) >> 4;
+#pragma unroll
+    for (int i = 0; i < NK; ++i) {
+        const int kx = 4 * i + kq;
+        bv[i] = (kx < K && cok) ? B[(size_t)kx * ldb + col] : 0.f;
+    }
+}
+
+template <int NK, bool PREFETCH>
+__device__ __forceinline__ void panel_run(const float *__restrict__ Pl, int ldp, int K, int S,
+                                          const float *__restrict__ B, int ldb,
+                                          float *__restrict__ W, int ldw, int tn0, int npan)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, kq = lane >> 4;
+    const int ntm = (K + 15) >> 4;
+    int col = (tn0 + wave) * 16 + (lane & 15);
+    float bv[NK];
+    panel_load_b<NK>(B, ldb, K, col, col < S, bv);
+    for (int pn = 0; pn < npan; ++pn) {
+        const bool cok = col < S;
+        const int ncol = col + 64;
+        float bn[NK];
+        if (PREFETCH && pn + 1 < npan) panel_load_b<NK>(B, ldb, K, ncol, ncol < S, bn);
+        for (int tm = 0; tm < ntm; ++tm) {
+            const int arow = tm * 16 + (lane & 15);
+            const float *ap = Pl + (arow < K ? arow : K - 1) * ldp + kq;
+            // A operands in groups of 8 k-steps: group g + 1 is read while group g's MFMAs
+            // run (the scheduling barriers keep that order)
+            constexpr int NG = (NK + 7) / 8;
+            float av[NK];
+            floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
+                if (g == 0) {
+#pragma unroll
+                    for (int i = 0; i < 8 && i < NK; ++i) av[i] = ap[4 * i];
+                }
+                if (g + 1 < NG) {
+#pragma unroll
+                    for (int i = 8 * (g + 1); i < 8 * (g + 2) && i < NK; ++i) av[i] = ap[4 * i];
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int i = 8 * g; i < 8 * (g + 1) && i < NK; ++i)
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[i], acc, 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            if (cok) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = tm * 16 + 4 * kq + v;
+                    if (r < K) W[(size_t)r * ldw + col] = acc[v];
+                }
+            }
+        }
+        if (pn + 1 < npan) {
+            if (PREFETCH) {
+#pragma unroll
+                for (int i = 0; i < NK; ++i) bv[i] = bn[i];
+            } else {
+                panel_load_b<NK>(B, ldb, K, ncol, ncol < S, bv);
+            }
+        }
+        col = ncol;
+    }
+}
+
+// One instantiation per k-step class [NKLO, NKHI] (1-8, 9-16, 17-32), so each launch
+// carries only the registers its own k range needs.
+template <int NKLO, int NKHI>
 __global__ __launch_bounds__(256) void batched_panel_kernel(const BatchDesc *__restrict__ desc,
                                                             const ContractItem *__restrict__ items,
                                                             int tau)
@@ -637,52 +726,85 @@ __global__ __launch_bounds__(256) void batched_panel_kernel(const BatchDesc *__r
     const BatchDesc d = desc[it.inst];
     const int t = d.T - tau + 1;
     if (t < 1) return;
-    const int K = d.K, S = d.S, ldp = K + 1;
+    const int K = d.K, S = d.S, ldp = panel_ld(K);
     const float *P = d.P + (size_t)(t - 1) * K * K;
-    for (int e = threadIdx.x; e < K * K; e += 256) {
-        const int r = e / K, c = e - r * K;
-        Pl[r * ldp + c] = P[e];
-    }
-    const float *B = ((d.T - t) & 1) ? d.vbuf1 : d.vbuf0;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int kq = lane >> 4;
-    const int col = (it.tn + wave) * 16 + (lane & 15);
-    const bool cok = col < S;
-    float bv[PANEL_KMAX / 4];
+    const int tid = threadIdx.x;
+    if ((K & 3) == 0 && (reinterpret_cast<uintptr_t>(P) & 15) == 0) {
+        // rows of K / 4 float4s, eight loads in flight per thread
+        const int k4 = K >> 2, n4 = K * k4;
+        const float4 *src = reinterpret_cast<const float4 *>(P);
+        for (int e0 = 0; e0 < n4; e0 += 8 * 256) {
+            // indices past the end are clamped to the last element: the same value is
+            // loaded and stored to the same place again, so no lane needs a branch
+            int e[8], o[8];
 #pragma unroll
-    for (int i = 0; i < PANEL_KMAX / 4; ++i) {
-        const int kx = 4 * i + kq;
-        bv[i] = (kx < K && cok) ? B[(size_t)kx * d.ld + col] : 0.f;
+            for (int u = 0; u < 8; ++u) {
+                e[u] = min(e0 + u * 256 + tid, n4 - 1);
+                const int r = e[u] / k4;
+                o[u] = r * ldp + 4 * (e[u] - r * k4);
+            }
+            const float4 v0 = src[e[0]], v1 = src[e[1]], v2 = src[e[2]], v3 = src[e[3]];
+            const float4 v4 = src[e[4]], v5 = src[e[5]], v6 = src[e[6]], v7 = src[e[7]];
+            float4 *dst = reinterpret_cast<float4 *>(Pl);
+            dst[o[0] >> 2] = v0; dst[o[1] >> 2] = v1; dst[o[2] >> 2] = v2; dst[o[3] >> 2] = v3;
+            dst[o[4] >> 2] = v4; dst[o[5] >> 2] = v5; dst[o[6] >> 2] = v6; dst[o[7] >> 2] = v7;
+        }
+    } else {
+        const int kp = ((K + 3) >> 2) << 2;     // zero columns K .. kp - 1
+        for (int e0 = 0; e0 < K * kp; e0 += 4 * 256) {
+            float v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = e0 + u * 256 + tid;
+                const int r = e / kp, c = e - r * kp;
+                v[u] = (e < K * kp && c < K) ? P[(size_t)r * K + c] : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = e0 + u * 256 + tid;
+                const int r = e / kp, c = e - r * kp;
+                if (e < K * kp) Pl[r * ldp + c] = v[u];
+            }
+        }
     }
     __syncthreads();
-    const int ntm = (K + 15) >> 4;
-    for (int tm = 0; tm < ntm; ++tm) {
-        const int arow = tm * 16 + (lane & 15);
-        const bool rok = arow < K;
-        floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int i = 0; i < PANEL_KMAX / 4; ++i) {
-            if (4 * i < K) {
-                const int kx = 4 * i + kq;
-                const float av = (kx < K && rok) ? Pl[arow * ldp + kx] : 0.f;
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[i], acc, 0, 0, 0);
-            }
-        }
-        if (cok) {
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int r = tm * 16 + 4 * kq + v;
-                if (r < K) d.W[(size_t)r * d.ld + col] = acc[v];
-            }
-        }
+    const float *B = ((d.T - t) & 1) ? d.vbuf1 : d.vbuf0;
+    switch ((K + 3) >> 2) {
+#define DP_PANEL_CASE(n)                                                                    \
+    case n:                                                                                 \
+        if constexpr (n >= NKLO && n <= NKHI)                                               \
+            panel_run<n, (NKHI <= 16)>(Pl, ldp, K, S, B, d.ld, d.W, d.ld, it.tn, it.tm);    \
+        break;
+        DP_PANEL_CASE(1) DP_PANEL_CASE(2) DP_PANEL_CASE(3) DP_PANEL_CASE(4)
+        DP_PANEL_CASE(5) DP_PANEL_CASE(6) DP_PANEL_CASE(7) DP_PANEL_CASE(8)
+        DP_PANEL_CASE(9) DP_PANEL_CASE(10) DP_PANEL_CASE(11) DP_PANEL_CASE(12)
+        DP_PANEL_CASE(13) DP_PANEL_CASE(14) DP_PANEL_CASE(15) DP_PANEL_CASE(16)
+        DP_PANEL_CASE(17) DP_PANEL_CASE(18) DP_PANEL_CASE(19) DP_PANEL_CASE(20)
+        DP_PANEL_CASE(21) DP_PANEL_CASE(22) DP_PANEL_CASE(23) DP_PANEL_CASE(24)
+        DP_PANEL_CASE(25) DP_PANEL_CASE(26) DP_PANEL_CASE(27) DP_PANEL_CASE(28)
+        DP_PANEL_CASE(29) DP_PANEL_CASE(30) DP_PANEL_CASE(31) DP_PANEL_CASE(32)
+#undef DP_PANEL_CASE
+        default: break;
     }
 }
+
+int panel_class(int K) { return K <= 32 ? 0 : (K <= 64 ? 1 : 2); }
 
 hipError_t launch_batched_panel(const BatchDesc *desc, const ContractItem *items, int n, int tau,
                                 int kmax, hipStream_t stream)
 {
-    const size_t lds = sizeof(float) * (size_t)kmax * (kmax + 1);
-    hipLaunchKernelGGL(batched_panel_kernel, dim3(n), dim3(256), lds, stream, desc, items, tau);
+    const size_t lds = sizeof(float) * (size_t)kmax * panel_ld(kmax);
+    switch (panel_class(kmax)) {
+        case 0:
+            hipLaunchKernelGGL((batched_panel_kernel<1, 8>), dim3(n), dim3(256), lds, stream, desc, items, tau);
+            break;
+        case 1:
+            hipLaunchKernelGGL((batched_panel_kernel<9, 16>), dim3(n), dim3(256), lds, stream, desc, items, tau);
+            break;
+        default:
+            hipLaunchKernelGGL((batched_panel_kernel<17, 32>), dim3(n), dim3(256), lds, stream, desc, items, tau);
+            break;
+    }
     return hipGetLastError();
 }
 

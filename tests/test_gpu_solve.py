@@ -123,7 +123,9 @@ def test_repeat_runs_are_bitwise_identical(dp):
 
 @pytest.mark.parametrize("shape", [(8, 16, 4, 4), (4, 16, 8, 8), (8, 8, 4, 4), (4, 8, 4, 2),
                                    (8, 16, 4, 2), (4, 16, 8, 4), (8, 8, 4, 1), (4, 8, 4, 1),
-                                   (8, 16, 4, 1), (4, 16, 4, 1), (4, 4, 4, 1), (8, 4, 4, 1)])
+                                   (8, 16, 4, 1), (4, 16, 4, 1), (4, 4, 4, 1), (8, 4, 4, 1),
+                                   (4, 8, 2, 1), (4, 4, 2, 1), (4, 8, 1, 1), (8, 8, 1, 1),
+                                   (4, 4, 1, 1)])
 def test_tile_shapes_give_bitwise_identical_results(dp, shape):
     inst = wl.random_small(31, 6, 21, 1100, 260, 180, c_start=3.0, lam_lo=-60.0)
     dp.set_sweep_shape()

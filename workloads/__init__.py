@@ -294,15 +294,35 @@ def iid_prices(T: int, R: int, *, seed: int, scale: float = 12.0, dof: float = 3
     real-time spread (Student t), the shape of the quantile forecasts of Sec. IV."""
     from scipy.stats import t as student_t
     rng = np.random.Generator(np.random.PCG64(seed))
-    h = np.arange(T) % 24
-    d = np.arange(T) // 24
-    da = 45.0 + 15.0 * np.sin(2 * np.pi * (h - 8) / 24.0) + 10.0 * np.sin(2 * np.pi * d / 366.0)
-    da = da + rng.normal(0.0, 5.0, T)
+    da, h = _day_ahead(T, rng)
     q = student_t.ppf((np.arange(R) + 0.5) / R, dof)
     spread = scale * (1.0 + 0.3 * np.sin(2 * np.pi * h / 24.0))[:, None] * q[None, :]
     lam = f32(da[:, None] + spread)
     prob = quantize_rows(np.full((T, R), 1.0 / R))
     return lam, prob
+
+
+def _day_ahead(T: int, rng):
+    """Hourly day-ahead curve: a daily and a yearly cycle plus Gaussian noise."""
+    h = np.arange(T) % 24
+    d = np.arange(T) // 24
+    da = 45.0 + 15.0 * np.sin(2 * np.pi * (h - 8) / 24.0) + 10.0 * np.sin(2 * np.pi * d / 366.0)
+    return da + rng.normal(0.0, 5.0, T), h
+
+
+def realized_prices(T: int, *, seed: int, scale: float = 12.0, dof: float = 3.0):
+    """One realised hourly real-time path [T] (FP32): the day-ahead curve of iid_prices
+    plus one Student-t draw of the spread (the perfect-foresight input of Sec. V-A)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    da, h = _day_ahead(T, rng)
+    spread = scale * (1.0 + 0.3 * np.sin(2 * np.pi * h / 24.0)) * rng.standard_t(dof, T)
+    return f32(da + spread)
+
+
+def negative_prices(lam):
+    """lam - max(lam) (<= 0 everywhere, the level shift of Sec. V-B), FP32."""
+    lam = np.asarray(lam, dtype=np.float64)
+    return f32(np.minimum(lam - lam.max(), 0.0))
 
 
 def table3_instance(hours: float, delta: float, *, T: int = 8784, R: int = 200, seed: int = 6):
