@@ -231,6 +231,8 @@ def main():
     ap.add_argument("--workload", default="day_5min")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--extra", default="year,adjoint,batch,table3",
+                    help="comma-separated extras to run after the headline line's steps")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the steps, copy 256 MiB device-to-device once (a kernel of known "
                          "traffic for calibrating hardware byte counters)")
@@ -270,17 +272,22 @@ def main():
         line["copy_probe_bytes"] = src.numel() * 4
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(inst)
-    if not args.no_extra:
+    wanted = set() if args.no_extra else {x for x in args.extra.split(",") if x}
+    if wanted:
         extra = {}
-        year = wl.year_hourly()
-        ysec, ytim = timed_solves(dp, torch, year, 2, 1)
-        extra["year_hourly"] = {"workload": year.name, "ms": round(ysec * 1e3, 2),
-                                "updates_per_s": round(year.candidates() / ysec, 1),
-                                "roofline": roofline_of(year, ytim)}
-        del year
-        extra["adjoint_vs_value"] = adjoint_ratio(dp, torch, wl.day_5min_adjoint())
-        extra["batched_vs_looped"] = batch_compare(dp, torch)
-        extra["table3_independent"] = table3_independent(dp, torch)
+        if "year" in wanted:
+            year = wl.year_hourly()
+            ysec, ytim = timed_solves(dp, torch, year, 2, 1)
+            extra["year_hourly"] = {"workload": year.name, "ms": round(ysec * 1e3, 2),
+                                    "updates_per_s": round(year.candidates() / ysec, 1),
+                                    "roofline": roofline_of(year, ytim)}
+            del year
+        if "adjoint" in wanted:
+            extra["adjoint_vs_value"] = adjoint_ratio(dp, torch, wl.day_5min_adjoint())
+        if "batch" in wanted:
+            extra["batched_vs_looped"] = batch_compare(dp, torch)
+        if "table3" in wanted:
+            extra["table3_independent"] = table3_independent(dp, torch)
         line["extra"] = extra
     print(json.dumps(line), flush=True)
 
