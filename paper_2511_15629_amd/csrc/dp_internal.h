@@ -80,6 +80,7 @@ struct IidArgs {
     const IidEnd *endc;      // charge endpoint table [S]
     const IidEnd *endd;      // discharge endpoint table [S]
     int R, S, w_up, w_down, P;
+    int TS, NP;              // outputs per block, partial sums per output (set by the launcher)
     Payoff pay;              // interior payoff (delta, eta_c = eta_d = eta, costs)
     float p_bar;
     const double *off_next;  // C_t (offset of Vin)
@@ -87,6 +88,10 @@ struct IidArgs {
     float *vabs;             // [S] absolute V_{t-1} (nullable)
     int16_t *pol;            // [R][S] action index into the ascending power grid (nullable)
 };
+struct IidShape {
+    int TS, threads, NP;
+};
+IidShape iid_shape(int R, int S);
 hipError_t launch_iid_stage(const IidArgs &a, hipStream_t stream);
 size_t iid_lds_bytes(int R, int S, int w_up, int w_down);
 hipError_t launch_iid_tables(int S, double delta, double eta, double p_bar, IidEnd *endc,

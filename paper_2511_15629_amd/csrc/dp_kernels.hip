@@ -380,12 +380,39 @@ hipError_t launch_sweep(const SweepArgs &a, const SweepShape &sh, hipStream_t st
 // with the exact first-argmax rescan; the two endpoint actions +-p_bar (interpolated
 // columns) are then compared in next-state order (discharge endpoint first, charge
 // endpoint last, strict >), giving the smallest maximising next state.  Q(s, r) goes to
-// LDS and V_{t-1}(s) = sum_r pi_r Q(s, r) is summed in ascending r (the expectation).
+// LDS; V_{t-1}(s) = sum_r pi_r Q(s, r) is formed by NP <= 16 threads per output, thread p
+// summing r = p, p + NP, ... in ascending order, and the NP partial sums added in ascending p.
+//
+// Launch shape (iid_shape): TS = ceil(S / 256) rounded up to a multiple of G, so a stage
+// has at most one block per CU; the block has 64 w threads with w chosen so that the
+// R TS / G units divide as evenly as possible over them.
 // ------------------------------------------------------------------------------------
-constexpr int IID_THREADS = 512;
 constexpr int IID_D = 8;
 constexpr int IID_G = 4;             // outputs per unit
-constexpr int IID_TS = 32;           // outputs per block
+
+IidShape iid_shape(int R, int S)
+{
+    IidShape sh;
+    const int per = (S + 255) / 256;
+    sh.TS = ((per + IID_G - 1) / IID_G) * IID_G;
+    const int units = R * (sh.TS / IID_G);
+    int best_w = 1;
+    double best = 1e30;
+    for (int w = 1; w <= 16; ++w) {
+        const int n = 64 * w;
+        const int iters = (units + n - 1) / n;
+        // cost: iterations of the busiest thread, then fewer idle lanes, then more threads
+        const double c = iters + 1e-3 * ((double)iters * n - units) / n - 1e-6 * w;
+        if (c < best) {
+            best = c;
+            best_w = w;
+        }
+    }
+    sh.threads = 64 * best_w;
+    // partial sums per output: about sqrt(R) balances the two sequential phases
+    sh.NP = std::max(1, std::min(sh.threads / sh.TS, 16));
+    return sh;
+}
 
 // Endpoint tables in FP64 with the formulas of Algorithm 1: sigma = s delta + F(p),
 // z = clip(sigma, 0, s_bar) / delta, z- = floor(z + 1e-9), z+ = ceil(z - 1e-9),
@@ -443,13 +470,13 @@ hipError_t launch_iid_init(float *V, int S, double *off, float *vabs, hipStream_
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(IID_THREADS) void iid_stage_kernel(IidArgs a)
+__global__ __launch_bounds__(1024) void iid_stage_kernel(IidArgs a)
 {
-    constexpr int D = IID_D, G = IID_G, TS = IID_TS;
+    constexpr int D = IID_D, G = IID_G;
     extern __shared__ float4 smem4[];
     float *smem = reinterpret_cast<float *>(smem4);
-    const int tid = threadIdx.x;
-    const int S = a.S, R = a.R;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int S = a.S, R = a.R, TS = a.TS, NP = a.NP;
     const int s0 = blockIdx.x * TS;
     const int s_end = min(s0 + TS, S);
     const int dlo = max(-a.w_down, -(s_end - 1));
@@ -457,28 +484,31 @@ __global__ __launch_bounds__(IID_THREADS) void iid_stage_kernel(IidArgs a)
     const int nchunk = (dhi - dlo + 1 + D - 1) / D;
     const int nrl = nchunk * D;
     // LDS: value halo over j in [s0 - w_down - 1, s0 + TS + w_up + 1] (-inf outside [0, S)),
-    // reward tables over the tile's interior moves, Q[R][TS].
+    // reward tables over the tile's interior moves, pi_t, Q[R][TS], partial sums [NP][TS].
     const int hb = s0 - a.w_down - 1;                      // first halo index
     const int nh = (TS + a.w_down + a.w_up + 3 + D + 3) & ~3;
     float *Vh = smem;
     float *gl = Vh + nh;
     float *hl = gl + nrl;
-    float *Q = hl + nrl;                                   // [R][TS]
+    float *pr = hl + nrl;
+    float *Q = pr + R;                                     // [R][TS]
+    float *part = Q + (size_t)R * TS;                      // [NP][TS]
     const float NEG = -INFINITY;
-    for (int i = tid; i < nh; i += IID_THREADS) {
+    for (int i = tid; i < nh; i += nth) {
         const int j = hb + i;
         Vh[i] = (j >= 0 && j < S) ? a.Vin[j] : NEG;
     }
-    for (int i = tid; i < nrl; i += IID_THREADS) {
+    for (int i = tid; i < nrl; i += nth) {
         const int d = dlo + i;
         gl[i] = move_energy(d, a.pay);
         hl[i] = (d <= dhi) ? move_cost(d, a.pay) : NEG;
     }
+    for (int i = tid; i < R; i += nth) pr[i] = a.prob[i];
     __syncthreads();
     const int ngrp = TS / G;
     const int units = R * ngrp;
     const int woff = s0 + dlo - hb;                        // halo index of the tile's first next state
-    for (int u = tid; u < units; u += IID_THREADS) {
+    for (int u = tid; u < units; u += nth) {
         const int r = u / ngrp, grp = u - r * ngrp;
         const int o0 = grp * G;                            // first output of the group (local)
         const float lam = a.lam[r];
@@ -544,13 +574,21 @@ __global__ __launch_bounds__(IID_THREADS) void iid_stage_kernel(IidArgs a)
         }
     }
     __syncthreads();
+    // expectation: NP partial sums per output (fixed order), then their ordered sum
+    for (int x = tid; x < NP * TS; x += nth) {
+        const int o = x % TS, p = x / TS;
+        float acc = 0.0f;
+        for (int r = p; r < R; r += NP) acc = fmaf(pr[r], Q[r * TS + o], acc);
+        part[p * TS + o] = acc;
+    }
+    __syncthreads();
     const float shift = a.Vin[0];
     const double Ct = a.off_next[0] + (double)shift;
-    for (int o = tid; o < TS; o += IID_THREADS) {
+    for (int o = tid; o < TS; o += nth) {
         const int s = s0 + o;
         if (s >= S) continue;
-        float acc = 0.0f;
-        for (int r = 0; r < R; ++r) acc = fmaf(a.prob[r], Q[r * TS + o], acc);
+        float acc = part[o];
+        for (int p = 1; p < NP; ++p) acc += part[p * TS + o];
         const float vn = acc - shift;
         a.Vout[s] = vn;
         if (a.vabs) a.vabs[s] = (float)((double)vn + Ct);
@@ -560,18 +598,23 @@ __global__ __launch_bounds__(IID_THREADS) void iid_stage_kernel(IidArgs a)
 
 size_t iid_lds_bytes(int R, int S, int w_up, int w_down)
 {
-    (void)S;
+    const IidShape sh = iid_shape(R, S);
     const int span = w_up + w_down + 1;
     const int nrl = ((span + IID_D - 1) / IID_D) * IID_D;
-    const int nh = (IID_TS + w_down + w_up + 3 + IID_D + 3) & ~3;
-    return sizeof(float) * ((size_t)nh + 2 * (size_t)nrl + (size_t)R * IID_TS);
+    const int nh = (sh.TS + w_down + w_up + 3 + IID_D + 3) & ~3;
+    return sizeof(float) * ((size_t)nh + 2 * (size_t)nrl + (size_t)R + (size_t)R * sh.TS +
+                            (size_t)sh.NP * sh.TS);
 }
 
-hipError_t launch_iid_stage(const IidArgs &a, hipStream_t stream)
+hipError_t launch_iid_stage(const IidArgs &a_in, hipStream_t stream)
 {
+    const IidShape sh = iid_shape(a_in.R, a_in.S);
+    IidArgs a = a_in;
+    a.TS = sh.TS;
+    a.NP = sh.NP;
     const size_t lds = iid_lds_bytes(a.R, a.S, a.w_up, a.w_down);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(iid_stage_kernel, dim3((a.S + IID_TS - 1) / IID_TS), dim3(IID_THREADS), lds,
+    hipLaunchKernelGGL(iid_stage_kernel, dim3((a.S + sh.TS - 1) / sh.TS), dim3(sh.threads), lds,
                        stream, a);
     return hipGetLastError();
 }
