@@ -181,11 +181,17 @@ size_t dp_iid_workspace_bytes(const dp_iid_problem *pb);
 int dp_solve_iid(const dp_iid_problem *pb, const float *lam, const float *prob, float *V,
                  int16_t *policy, void *ws, size_t ws_bytes, void *stream);
 
-/* Batched solves of many independent instances in one persistent launch.
- * A plan owns a device work table, its device workspace and a captured HIP graph; it
- * is created once for a fixed list of problems (host array probs[n]) and replayed with
- * new data.  tune_cache: path of a text cache of autotuned tile shapes (created or
- * extended), or NULL to use built-in defaults without tuning. */
+/* Batched solves of many independent instances (not in the paper; Sec. V's duration sweeps
+ * are such batches).  All instances advance stage-synchronously: batch stage tau puts
+ * instance i at its own stage T_i - tau + 1, and each tau is one expectation launch per
+ * K class plus one sweep launch per tile class.  A plan owns the device descriptor table,
+ * the work tables, its device workspace (one solver region per instance) and a HIP graph of
+ * the whole launch sequence, captured once at creation; it is created for a fixed list of
+ * problems (host array probs[n], flags must be 0, ckpt_every ignored) and replayed with new
+ * data.  tune_cache: path of a text cache of autotuned sweep tile shapes (created or
+ * extended; the fastest shape per move-span class, timed at creation), or NULL to use the
+ * built-in shapes without tuning.  Errors: DP_EINVAL (bad problem or pointer), DP_ENOMEM,
+ * DP_EHIP.  The plan must be destroyed with dp_batch_plan_destroy. */
 typedef struct dp_batch_plan dp_batch_plan;
 
 int dp_batch_plan_create(dp_batch_plan **out, int n, const dp_problem *probs,
@@ -193,9 +199,12 @@ int dp_batch_plan_create(dp_batch_plan **out, int n, const dp_problem *probs,
 
 /* Solve every instance i: lam[i] [T_i][K_i], P[i] [T_i][K_i][K_i] (device pointers held
  * in HOST arrays of length n), outputs V1[i] [K_i][S_i] and policy[i] [T_i][K_i][S_i]
- * (policy[i] may be NULL for all i or none).  Terminal values are zero.  The first call
- * captures a graph keyed on the pointer set; later calls with the same pointers replay
- * it, new pointers re-capture. */
+ * (policy may be NULL, or an array with a pointer for every instance).  Terminal values
+ * are zero.  Each call copies the pointers into the device descriptor table (from a pinned
+ * staging buffer, asynchronously on `stream`) and replays the graph on `stream`, so new
+ * pointers need no re-capture.  Results are bitwise those of dp_batch_solve_looped.
+ * Calls on one plan must be ordered: issue them on one stream, or synchronise between
+ * them, since every call rewrites the same descriptor table and workspace. */
 int dp_batch_solve(dp_batch_plan *plan, const float *const *lam, const float *const *P,
                    float *const *V1, int16_t *const *policy, void *stream);
 

@@ -48,7 +48,7 @@ int span_bucket(int span)
 {
     int b = 0;
     while ((32 << b) < span && b < 10) ++b;
-    return b;   // spans (16 << b, 32 << b]
+    return b;   // spans (16 << b, 32 << b]; bucket 0 also takes every span <= 16
 }
 
 bool shape_fits(const dpk::SweepShape &sh, int w_up, int w_down)
@@ -368,7 +368,7 @@ int dp_batch_plan_create(dp_batch_plan **out, int n, const dp_problem *probs,
     for (auto &kv : buckets) {
         TileClass c;
         c.inst = kv.second;
-        c.span_lo = (16 << kv.first) + 1;
+        c.span_lo = kv.first == 0 ? 1 : (16 << kv.first) + 1;
         c.span_hi = 32 << kv.first;
         c.sh = pick_shape(&p->probs[c.inst[0]]);
         auto it = cached.find(kv.first);

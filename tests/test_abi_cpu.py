@@ -96,3 +96,51 @@ def test_checkpoint_size_counts_interior_slots(L):
     slots = (288 - 1) // 16
     assert n >= slots * 100 * 1001 * 4 + slots * 8
     assert n < (slots + 1) * 100 * 1001 * 4 + 4096
+
+
+def _iid(**kw):
+    from paper_2511_15629_amd import _lib
+    f = dict(T=4, R=5, S=41, reserved=0, delta=0.1, eta=0.9219544, p_bar=1.0, flags=0)
+    f.update(kw)
+    return _lib.IidProblem(**f)
+
+
+def test_iid_struct_and_action_grid_match_the_paper(L):
+    # P counts of Table 1 at eta = sqrt(0.85), p_bar = 1 (tests/golden/grid_counts.txt)
+    from paper_2511_15629_amd import _lib
+    assert ctypes.sizeof(_lib.IidProblem) == 32
+    golden = {}
+    for line in open(os.path.join(ROOT, "tests", "golden", "grid_counts.txt")):
+        parts = line.split()
+        if parts and parts[0] == "P":
+            golden[float(parts[1])] = int(parts[3])
+    for delta, want in golden.items():
+        pb = _iid(delta=delta)
+        P, nc, nd = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        assert L.dp_iid_action_grid(ctypes.byref(pb), ctypes.byref(P), ctypes.byref(nc),
+                                    ctypes.byref(nd)) == 0
+        assert P.value == want and nc.value + nd.value + 1 == want
+
+
+@pytest.mark.parametrize("bad", [dict(T=0), dict(R=0), dict(R=5000), dict(S=1), dict(S=40000),
+                                 dict(delta=0.0), dict(eta=1.5), dict(eta=0.0), dict(p_bar=0.0),
+                                 dict(p_bar=float("inf")), dict(flags=0x2), dict(reserved=1),
+                                 dict(delta=1e-5)])
+def test_invalid_iid_problems_are_rejected_on_the_host(L, bad):
+    pb = _iid(**bad)
+    assert L.dp_iid_workspace_bytes(ctypes.byref(pb)) == 0
+    rc = L.dp_solve_iid(ctypes.byref(pb), 1, 1, 1, None, 256, 1 << 20, None)
+    assert rc in (-1, -7)
+    assert L.dp_last_error()
+
+
+def test_iid_lds_limit_and_workspace_rules(L):
+    # R = 4096 samples over a 32767-level grid need more LDS per block than a CU holds
+    pb = _iid(R=4096, S=32767, delta=0.01)
+    assert L.dp_solve_iid(ctypes.byref(pb), 1, 1, 1, None, 256, 1 << 30, None) == -7
+    pb = _iid()
+    need = L.dp_iid_workspace_bytes(ctypes.byref(pb))
+    assert need > 0
+    assert L.dp_solve_iid(ctypes.byref(pb), None, 1, 1, None, 256, need, None) == -1
+    assert L.dp_solve_iid(ctypes.byref(pb), 1, 1, 1, None, 256, need - 1, None) == -3
+    assert L.dp_solve_iid(ctypes.byref(pb), 1, 1, 1, None, 0x1001, need, None) == -1
