@@ -93,18 +93,31 @@ int validate_problem(const dp_problem *pb)
     if (!(st.c_start >= 0.0f) || !isfinite(st.c_start)) return fail(DP_EINVAL, "c_start must be finite and >= 0");
     if (pb->flags & ~(uint32_t)(DP_STORE_V_ALL | DP_VALIDATE)) return fail(DP_EINVAL, "unknown flag bits 0x%x", pb->flags);
     if (pb->ckpt_every < 0) return fail(DP_EINVAL, "ckpt_every must be >= 0");
+    if (pick_shape(pb).R == 0)
+        return fail(DP_ENOTSUP, "move window %d..%d needs more LDS than a CU holds",
+                    -st.w_down, st.w_up);
     return DP_OK;
+}
+
+static bool fits(const dpk::SweepShape &sh, const dp_problem *pb)
+{
+    return dpk::sweep_lds_bytes(sh, pb->st.w_up, pb->st.w_down) <= 160 * 1024;
 }
 
 dpk::SweepShape pick_shape(const dp_problem *pb)
 {
-    if (g_shape_override.R) return g_shape_override;
+    const dpk::SweepShape none{0, 0, 0, 0};
+    if (g_shape_override.R) return fits(g_shape_override, pb) ? g_shape_override : none;
     const int span = pb->st.w_up + pb->st.w_down + 1;
     // Long move ranges: 8 outputs per lane, the range split over 8 waves (measured best
-    // on the 100 x 1001 and 50 x 2001 grids); short ranges: fewer splits.
-    if (span >= 256) return dpk::SweepShape{8, 16, 8, 8};
-    if (span >= 64) return dpk::SweepShape{4, 16, 4, 4};
-    return dpk::SweepShape{4, 8, 4, 2};
+    // on the 100 x 1001 and 50 x 2001 grids); short ranges: fewer splits.  Windows too wide
+    // for those tiles' LDS fall back to one wave of 256 outputs (the least LDS per span).
+    dpk::SweepShape sh = span >= 256 ? dpk::SweepShape{8, 16, 8, 8}
+                         : span >= 64 ? dpk::SweepShape{4, 16, 4, 4}
+                                      : dpk::SweepShape{4, 8, 4, 2};
+    if (fits(sh, pb)) return sh;
+    sh = dpk::SweepShape{4, 8, 1, 1};
+    return fits(sh, pb) ? sh : none;
 }
 
 SolveLayout solve_layout(const dp_problem *pb)

@@ -144,3 +144,13 @@ def test_iid_lds_limit_and_workspace_rules(L):
     assert L.dp_solve_iid(ctypes.byref(pb), None, 1, 1, None, 256, need, None) == -1
     assert L.dp_solve_iid(ctypes.byref(pb), 1, 1, 1, None, 256, need - 1, None) == -3
     assert L.dp_solve_iid(ctypes.byref(pb), 1, 1, 1, None, 0x1001, need, None) == -1
+
+
+def test_windows_beyond_lds_are_rejected_before_device_work(L):
+    # a +-12000 window needs more LDS than any tile shape has; +-9000 fits the one-wave tile
+    pb = _pb(S=32767, w_up=12000, w_down=12000)
+    assert L.dp_workspace_bytes(ctypes.byref(pb)) == 0
+    assert L.dp_solve(ctypes.byref(pb), 1, 1, None, 1, None, None, 256, 1 << 30, None) == -7
+    assert b"LDS" in L.dp_last_error()
+    pb = _pb(S=32767, w_up=9000, w_down=9000)
+    assert L.dp_workspace_bytes(ctypes.byref(pb)) > 0

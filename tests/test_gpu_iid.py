@@ -113,3 +113,24 @@ def test_table3_large_sampled_stages(dp, hours, delta):
         check_policy(pol, Q_all, v_or)
     del out
     torch.cuda.empty_cache()
+
+
+def test_maximum_grid_sampled_stages(dp):
+    """S = 32767 levels (the int16 limit) with P = 2013 actions and 3 samples."""
+    T, R, S, delta, eta, p_bar = 3, 3, 32767, 0.001, 0.9, 1.0
+    lam, prob = wl.iid_prices(T, R, seed=77)
+    out = dp.solve_independent(dev(lam), dev(prob), S, delta, eta, p_bar, store_all=True,
+                               policy=True)
+    torch.cuda.synchronize()
+    s_hat, p_hat, _, _ = grid(S, delta, eta, p_bar)
+    assert p_hat.shape[0] == 2013
+    pre = alg1.precompute(s_hat, p_hat, float(np.float32(eta)))
+    rows = np.unique(np.concatenate([np.arange(0, 40), np.linspace(0, S - 1, 61).astype(np.int64),
+                                     np.arange(S - 40, S)]))
+    for t in range(T, 0, -1):
+        v_next = out["V"][t].cpu().numpy().astype(np.float64)
+        v_gpu = out["V"][t - 1].cpu().numpy()
+        v_or, Q_all = alg1.stage(pre, p_hat, lam[t - 1], prob[t - 1], v_next, rows=rows)
+        scale = max(float(np.max(np.abs(v_or))), float(np.max(np.abs(v_gpu))), 1e-30)
+        assert float(np.max(np.abs(v_gpu[rows] - v_or))) <= RTOL * scale, t
+        check_policy(out["policy"][t - 1].cpu().numpy()[:, rows], Q_all, v_or)

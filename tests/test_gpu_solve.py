@@ -68,6 +68,20 @@ def test_ragged_shapes_match_oracle(dp, case):
     print(f"{inst.name}: accepted near-tie policy mismatches = {n}")
 
 
+@pytest.mark.parametrize("case", [dict(seed=21, T=3, K=2, S=32767, wu=7000, wd=7000),
+                                  dict(seed=22, T=2, K=2, S=32767, wu=9000, wd=9000),
+                                  dict(seed=23, T=2, K=1024, S=64, wu=8, wd=8)],
+                         ids=["S_max_window_7000", "S_max_window_9000", "K_max"])
+def test_maximum_sizes_match_oracle(dp, case):
+    # S = DP_MAX_S with the widest windows the preferred tile and the one-wave fallback tile
+    # hold in LDS, and K = DP_MAX_K
+    kw = dict(case)
+    seed, T, K, S, wu, wd = (kw.pop(k) for k in ("seed", "T", "K", "S", "wu", "wd"))
+    inst = wl.random_small(seed, T, K, S, wu, wd, delta=0.001)
+    n, V, pol, ref = full_parity(dp, inst)
+    print(f"{inst.name}: accepted near-tie policy mismatches = {n}")
+
+
 def test_hourly_day_small_matches_oracle(dp):
     inst = wl.day_hourly_small()
     n, V, pol, ref = full_parity(dp, inst)
