@@ -207,16 +207,37 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
     int *pc = reinterpret_cast<int *>(pb + NSPLIT * TS);
 
     const int tid = threadIdx.x;
-    const float lam = a.lam[k];
     const float NEG = -INFINITY;
+    // Every global value the block needs is requested before any is waited for, so the
+    // block pays one memory round trip rather than one per dependent load: the W row over
+    // the reachable next states (four loads per thread in flight), then lam_t[k], the
+    // stage's normalisation constant W_t[0][0] and the offset C_{t+1} (for the epilogue).
+    const float *Wk = a.W + (size_t)k * a.ldw;
+    float lam = 0.0f, shift = 0.0f;
+    double off_next = 0.0;
+    for (int i4 = 0; i4 < nwl; i4 += 4 * NW * 64) {     // nwl > 0: at least one pass
+        float w[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = i4 + u * NW * 64 + tid;
+            const int j = s0 + dlo + i;
+            w[u] = (i < nwl && j >= 0 && j < S) ? Wk[j] : NEG;
+        }
+        if (i4 == 0) {
+            __builtin_amdgcn_sched_barrier(0);      // the scalar loads go out after these
+            lam = a.lam[k];
+            shift = a.W[0];
+            off_next = a.off_next[0];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = i4 + u * NW * 64 + tid;
+            if (i < nwl) Wl[i] = w[u];
+        }
+    }
     for (int i = tid; i < nrl; i += NW * 64) {
         const int d = dlo + i;
         rl[i] = (d <= dhi) ? move_reward(lam, d, a.pay) : NEG;
-    }
-    const float *Wk = a.W + (size_t)k * a.ldw;
-    for (int i = tid; i < nwl; i += NW * 64) {
-        const int j = s0 + dlo + i;
-        Wl[i] = (j >= 0 && j < S) ? Wk[j] : NEG;
     }
     __syncthreads();
 
@@ -270,8 +291,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
     }
     __syncthreads();
 
-    const float shift = a.W[0];    // W_t[0][0]: this stage's normalisation constant
-    const double Ct = a.off_next[0] + (double)shift;
+    const double Ct = off_next + (double)shift;   // shift = W_t[0][0], the normalisation
     for (int o = tid; o < TS; o += NW * 64) {
         const int s = s0 + o;
         if (s >= S) break;
