@@ -89,7 +89,7 @@ struct IidArgs {
     int16_t *pol;            // [R][S] action index into the ascending power grid (nullable)
 };
 struct IidShape {
-    int TS, threads, NP;
+    int TS, threads, NP, RB;   // outputs per block, threads, partial sums, samples per unit
 };
 IidShape iid_shape(int R, int S);
 hipError_t launch_iid_stage(const IidArgs &a, hipStream_t stream);

@@ -395,7 +395,9 @@ hipError_t launch_sweep(const SweepArgs &a, const SweepShape &sh, hipStream_t st
 // One launch per stage.  Block = a tile of TS SoC indices for all R price samples; the
 // value row V_t over every next state the tile can reach is staged in LDS once and shared
 // by the R samples (in this model the continuation value does not depend on the sample).
-// Work unit = (sample r, group of G consecutive outputs): the interior moves (whole grid
+// Work unit = (RB consecutive samples, group of G consecutive outputs); the value window
+// and move tables of each chunk are read from LDS once for the RB samples.  Per sample and
+// output, the interior moves (whole grid
 // steps, Algorithm 1's non-interpolated columns) run through the chunked max-plus loop
 // with the exact first-argmax rescan; the two endpoint actions +-p_bar (interpolated
 // columns) are then compared in next-state order (discharge endpoint first, charge
@@ -405,17 +407,22 @@ hipError_t launch_sweep(const SweepArgs &a, const SweepShape &sh, hipStream_t st
 //
 // Launch shape (iid_shape): TS = ceil(S / 256) rounded up to a multiple of G, so a stage
 // has at most one block per CU; the block has 64 w threads with w chosen so that the
-// R TS / G units divide as evenly as possible over them.
+// ceil(R / RB) TS / G units divide as evenly as possible over them.
 // ------------------------------------------------------------------------------------
 constexpr int IID_D = 8;
 constexpr int IID_G = 4;             // outputs per unit
+// price samples per unit (they share the LDS reads): 4 when the block still has at least
+// four waves of units, else 1 (small grids are latency-bound and need the threads)
+constexpr int IID_RB_MAX = 4;
 
 IidShape iid_shape(int R, int S)
 {
     IidShape sh;
     const int per = (S + 255) / 256;
     sh.TS = ((per + IID_G - 1) / IID_G) * IID_G;
-    const int units = R * (sh.TS / IID_G);
+    const int ngrp = sh.TS / IID_G;
+    sh.RB = ((R + IID_RB_MAX - 1) / IID_RB_MAX) * ngrp >= 256 ? IID_RB_MAX : 1;
+    const int units = ((R + sh.RB - 1) / sh.RB) * ngrp;
     int best_w = 1;
     double best = 1e30;
     for (int w = 1; w <= 16; ++w) {
@@ -490,6 +497,7 @@ hipError_t launch_iid_init(float *V, int S, double *off, float *vabs, hipStream_
     return hipGetLastError();
 }
 
+template <int RB>
 __global__ __launch_bounds__(1024) void iid_stage_kernel(IidArgs a)
 {
     constexpr int D = IID_D, G = IID_G;
@@ -504,93 +512,137 @@ __global__ __launch_bounds__(1024) void iid_stage_kernel(IidArgs a)
     const int nchunk = (dhi - dlo + 1 + D - 1) / D;
     const int nrl = nchunk * D;
     // LDS: value halo over j in [s0 - w_down - 1, s0 + TS + w_up + 1] (-inf outside [0, S)),
-    // reward tables over the tile's interior moves, pi_t, Q[R][TS], partial sums [NP][TS].
+    // reward tables over the tile's interior moves, lam_t and pi_t, Q[R][TS], partial sums
+    // [NP][TS].
     const int hb = s0 - a.w_down - 1;                      // first halo index
     const int nh = (TS + a.w_down + a.w_up + 3 + D + 3) & ~3;
     float *Vh = smem;
     float *gl = Vh + nh;
     float *hl = gl + nrl;
     float *pr = hl + nrl;
-    float *Q = pr + R;                                     // [R][TS]
+    float *pl = pr + R;
+    float *Q = pl + R;                                     // [R][TS]
     float *part = Q + (size_t)R * TS;                      // [NP][TS]
     const float NEG = -INFINITY;
-    for (int i = tid; i < nh; i += nth) {
+    // one pass issues every global load (value halo, pi_t, lam_t, and behind them V_t[0]
+    // and C_{t+1} for the epilogue) before any is used; nload > TS, so every thread that
+    // writes an output makes at least one pass
+    const int nload = max(nh, R);
+    float shift = 0.0f;
+    double off_next = 0.0;
+    for (int i = tid; i < nload; i += nth) {
         const int j = hb + i;
-        Vh[i] = (j >= 0 && j < S) ? a.Vin[j] : NEG;
+        const float v = (i < nh && j >= 0 && j < S) ? a.Vin[j] : NEG;
+        const float pv = i < R ? a.prob[i] : 0.0f;
+        const float lv = i < R ? a.lam[i] : 0.0f;
+        if (i == tid) {
+            __builtin_amdgcn_sched_barrier(0);
+            shift = a.Vin[0];                              // V_t[0]: the normalisation
+            off_next = a.off_next[0];
+        }
+        if (i < nh) Vh[i] = v;
+        if (i < R) {
+            pr[i] = pv;
+            pl[i] = lv;
+        }
     }
     for (int i = tid; i < nrl; i += nth) {
         const int d = dlo + i;
         gl[i] = move_energy(d, a.pay);
         hl[i] = (d <= dhi) ? move_cost(d, a.pay) : NEG;
     }
-    for (int i = tid; i < R; i += nth) pr[i] = a.prob[i];
     __syncthreads();
     const int ngrp = TS / G;
-    const int units = R * ngrp;
+    const int nrb = (R + RB - 1) / RB;
+    const int units = nrb * ngrp;
     const int woff = s0 + dlo - hb;                        // halo index of the tile's first next state
+    // work unit = (RB consecutive samples, G consecutive outputs): the value window and the
+    // move tables of a chunk are read once for the RB samples
     for (int u = tid; u < units; u += nth) {
-        const int r = u / ngrp, grp = u - r * ngrp;
+        const int rb = u / ngrp, grp = u - rb * ngrp;
         const int o0 = grp * G;                            // first output of the group (local)
-        const float lam = a.lam[r];
         const float *Wl = Vh + woff + o0;
-        float best[G];
-        int cid[G];
+        float lamq[RB];
 #pragma unroll
-        for (int i = 0; i < G; ++i) {
-            best[i] = NEG;
-            cid[i] = 0;
+        for (int q = 0; q < RB; ++q) {
+            const int r = rb * RB + q;
+            lamq[q] = r < R ? pl[r] : 0.0f;
         }
-        for (int c = 0; c < nchunk; ++c) {
-            float w[G + D];
+        float best[RB][G];
+        int cid[RB][G];
 #pragma unroll
-            for (int m = 0; m < G + D - 1; ++m) w[m] = Wl[c * D + m];
-            float rr[D];
-#pragma unroll
-            for (int d = 0; d < D; ++d) rr[d] = fmaf(lam, gl[c * D + d], hl[c * D + d]);
+        for (int q = 0; q < RB; ++q)
 #pragma unroll
             for (int i = 0; i < G; ++i) {
-                float m = best[i];
+                best[q][i] = NEG;
+                cid[q][i] = 0;
+            }
+        for (int c = 0; c < nchunk; ++c) {
+            float w[G + D], gg[D], hh[D];
 #pragma unroll
-                for (int d = 0; d < D; ++d) m = fmaxf(m, w[i + d] + rr[d]);
-                cid[i] = (m > best[i]) ? c : cid[i];
-                best[i] = m;
+            for (int m = 0; m < G + D - 1; ++m) w[m] = Wl[c * D + m];
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                gg[d] = gl[c * D + d];
+                hh[d] = hl[c * D + d];
+            }
+#pragma unroll
+            for (int q = 0; q < RB; ++q) {
+                float rr[D];
+#pragma unroll
+                for (int d = 0; d < D; ++d) rr[d] = fmaf(lamq[q], gg[d], hh[d]);
+#pragma unroll
+                for (int i = 0; i < G; ++i) {
+                    float m = best[q][i];
+#pragma unroll
+                    for (int d = 0; d < D; ++d) m = fmaxf(m, w[i + d] + rr[d]);
+                    cid[q][i] = (m > best[q][i]) ? c : cid[q][i];
+                    best[q][i] = m;
+                }
             }
         }
 #pragma unroll
-        for (int i = 0; i < G; ++i) {
-            const int s = s0 + o0 + i;
-            if (s >= S) continue;
-            // first interior move attaining the maximum
-            int arg = 0;
-            for (int d = D - 1; d >= 0; --d) {
-                const float x = Wl[cid[i] * D + i + d] + fmaf(lam, gl[cid[i] * D + d], hl[cid[i] * D + d]);
-                if (x == best[i]) arg = d;
-            }
-            const int dstar = dlo + cid[i] * D + arg;      // interior move (next state s + dstar)
-            float q = best[i];
-            int act = a.w_up + 1 - dstar;                  // ascending-power index of that move
-            // discharge endpoint: smallest next state, wins ties
-            const IidEnd ed = a.endd[s];
-            if (ed.lo >= 0) {
-                const float vl = Vh[ed.lo - hb], vh = Vh[ed.hi - hb];
-                const float x = fmaf(lam, a.p_bar, (1.0f - ed.b) * vl + ed.b * vh);
-                if (x >= q) {
-                    q = x;
-                    act = a.P - 1;
+        for (int q = 0; q < RB; ++q) {
+            const int r = rb * RB + q;
+            if (r >= R) break;
+            const float lam = lamq[q];
+#pragma unroll
+            for (int i = 0; i < G; ++i) {
+                const int s = s0 + o0 + i;
+                if (s >= S) continue;
+                // first interior move attaining the maximum
+                int arg = 0;
+                for (int d = D - 1; d >= 0; --d) {
+                    const float x = Wl[cid[q][i] * D + i + d] +
+                                    fmaf(lam, gl[cid[q][i] * D + d], hl[cid[q][i] * D + d]);
+                    if (x == best[q][i]) arg = d;
                 }
-            }
-            // charge endpoint: largest next state, loses ties
-            const IidEnd ec = a.endc[s];
-            if (ec.lo >= 0) {
-                const float vl = Vh[ec.lo - hb], vh = Vh[ec.hi - hb];
-                const float x = fmaf(lam, -a.p_bar, (1.0f - ec.b) * vl + ec.b * vh);
-                if (x > q) {
-                    q = x;
-                    act = 0;
+                const int dstar = dlo + cid[q][i] * D + arg;   // interior move (next state s + dstar)
+                float qv = best[q][i];
+                int act = a.w_up + 1 - dstar;                  // ascending-power index of that move
+                // discharge endpoint: smallest next state, wins ties
+                const IidEnd ed = a.endd[s];
+                if (ed.lo >= 0) {
+                    const float vl = Vh[ed.lo - hb], vh = Vh[ed.hi - hb];
+                    const float x = fmaf(lam, a.p_bar, (1.0f - ed.b) * vl + ed.b * vh);
+                    if (x >= qv) {
+                        qv = x;
+                        act = a.P - 1;
+                    }
                 }
+                // charge endpoint: largest next state, loses ties
+                const IidEnd ec = a.endc[s];
+                if (ec.lo >= 0) {
+                    const float vl = Vh[ec.lo - hb], vh = Vh[ec.hi - hb];
+                    const float x = fmaf(lam, -a.p_bar, (1.0f - ec.b) * vl + ec.b * vh);
+                    if (x > qv) {
+                        qv = x;
+                        act = 0;
+                    }
+                }
+                Q[r * TS + o0 + i] = qv;
+                if (a.pol) a.pol[(size_t)r * S + s] = (int16_t)act;
             }
-            Q[r * TS + o0 + i] = q;
-            if (a.pol) a.pol[(size_t)r * S + s] = (int16_t)act;
         }
     }
     __syncthreads();
@@ -602,8 +654,7 @@ __global__ __launch_bounds__(1024) void iid_stage_kernel(IidArgs a)
         part[p * TS + o] = acc;
     }
     __syncthreads();
-    const float shift = a.Vin[0];
-    const double Ct = a.off_next[0] + (double)shift;
+    const double Ct = off_next + (double)shift;
     for (int o = tid; o < TS; o += nth) {
         const int s = s0 + o;
         if (s >= S) continue;
@@ -622,7 +673,7 @@ size_t iid_lds_bytes(int R, int S, int w_up, int w_down)
     const int span = w_up + w_down + 1;
     const int nrl = ((span + IID_D - 1) / IID_D) * IID_D;
     const int nh = (sh.TS + w_down + w_up + 3 + IID_D + 3) & ~3;
-    return sizeof(float) * ((size_t)nh + 2 * (size_t)nrl + (size_t)R + (size_t)R * sh.TS +
+    return sizeof(float) * ((size_t)nh + 2 * (size_t)nrl + 2 * (size_t)R + (size_t)R * sh.TS +
                             (size_t)sh.NP * sh.TS);
 }
 
@@ -634,8 +685,11 @@ hipError_t launch_iid_stage(const IidArgs &a_in, hipStream_t stream)
     a.NP = sh.NP;
     const size_t lds = iid_lds_bytes(a.R, a.S, a.w_up, a.w_down);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(iid_stage_kernel, dim3((a.S + sh.TS - 1) / sh.TS), dim3(sh.threads), lds,
-                       stream, a);
+    const dim3 grid((a.S + sh.TS - 1) / sh.TS);
+    if (sh.RB == IID_RB_MAX)
+        hipLaunchKernelGGL(iid_stage_kernel<IID_RB_MAX>, grid, dim3(sh.threads), lds, stream, a);
+    else
+        hipLaunchKernelGGL(iid_stage_kernel<1>, grid, dim3(sh.threads), lds, stream, a);
     return hipGetLastError();
 }
 
