@@ -323,10 +323,12 @@ int dp_batch_plan_create(dp_batch_plan **out, int n, const dp_problem *probs,
         // LDS); otherwise one item = a strip of four adjacent 16 x 16 tiles of one row tile
         const int ntm = (pb.K + 15) / 16, ntn = (pb.st.S + 15) / 16;
         if (pb.K <= 128) {
-            // items of up to four panels (P_t staged once per item)
+            // items of up to four panels (P_t staged once per item); two for K > 64, whose
+            // items are long enough that finer ones balance the CUs better
             const int c = dpk::panel_class(pb.K);
-            for (int tn = 0; tn < ntn; tn += 16)
-                pclass[c].push_back({i, std::min(4, (ntn - tn + 3) / 4), tn});
+            const int ppi = c == 2 ? 2 : 4;
+            for (int tn = 0; tn < ntn; tn += 4 * ppi)
+                pclass[c].push_back({i, std::min(ppi, (ntn - tn + 3) / 4), tn});
             p->pan_kmax[c] = std::max(p->pan_kmax[c], pb.K);
         } else {
             for (int tn = 0; tn < ntn; tn += 4)
