@@ -1082,27 +1082,29 @@ hipError_t launch_adjoint_scale(const float *seed, size_t n, double *scale, hipS
 }
 
 // ------------------------------------------------------------------------------------
-// One launch for the two products that consume nu_t:
-//   blocks [0, nG):  grad_P_t = nu_t V_{t+1}^T, one 16 x 16 tile per block, four waves
-//                    each reducing a quarter of j in chunks of prefetched MFMA steps,
-//                    the partial tiles added in wave order;
-//   blocks [nG, ..): mu_{t+1} = P_t^T nu_t, the expectation tile function with A = P^T.
+// One launch for the two products that consume nu_t, 16 waves per block:
+//   blocks [0, nG):  grad_P_t = nu_t V_{t+1}^T, one 16 x 16 tile per block; wave w reduces
+//                    the w-th sixteenth of j (one chunk of prefetched MFMA steps), and the
+//                    16 partial tiles are added in wave order;
+//   blocks [nG, ..): mu_{t+1} = P_t^T nu_t, the expectation tile function with A = P^T,
+//                    one tile per wave.
 // ------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void adjoint_mix_kernel(const float *__restrict__ nu, int ldn,
-                                                          const float *__restrict__ V, int K,
-                                                          int S, const float *__restrict__ Pt,
-                                                          float *__restrict__ gP,
-                                                          float *__restrict__ mu, int ldm,
-                                                          int nG)
+constexpr int MIX_WAVES = 16;
+
+__global__ __launch_bounds__(64 * MIX_WAVES) void adjoint_mix_kernel(
+    const float *__restrict__ nu, int ldn, const float *__restrict__ V, int K, int S,
+    const float *__restrict__ Pt, float *__restrict__ gP, float *__restrict__ mu, int ldm, int nG)
 {
     constexpr int CH = 16;
-    __shared__ float part[4][256];
+    __shared__ float part[MIX_WAVES][256];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     if ((int)blockIdx.x >= nG) {
         const int ntm = (K + 15) >> 4, ntn = (S + 15) >> 4;
-        const int wid = (blockIdx.x - nG) * 4 + wave;
+        const int wid = (blockIdx.x - nG) * MIX_WAVES + wave;
         if (wid >= ntm * ntn) return;
-        contract_tile<true, 32>(Pt, nu, ldn, mu, ldm, K, S, wid % ntm, wid / ntm);
+        // chunks of 16 steps keep the 1024-thread block within its registers; the chunk
+        // size changes only when loads are issued, not the MFMA chain
+        contract_tile<true, 16>(Pt, nu, ldn, mu, ldm, K, S, wid % ntm, wid / ntm);
         return;
     }
     const int ntm = (K + 15) >> 4;
@@ -1112,7 +1114,7 @@ __global__ __launch_bounds__(256) void adjoint_mix_kernel(const float *__restric
     const int bcol = tn * 16 + (lane & 15);   // k'
     const bool rok = arow < K, cok = bcol < K;
     const int steps = (S + 3) / 4;
-    const int per = (steps + 3) / 4;
+    const int per = (steps + MIX_WAVES - 1) / MIX_WAVES;
     const int jb = wave * per * 4, je = min(S, (wave + 1) * per * 4);
     floatx4 acc = {0.f, 0.f, 0.f, 0.f};
     for (int j0 = jb; j0 < je; j0 += 4 * CH) {
@@ -1131,10 +1133,14 @@ __global__ __launch_bounds__(256) void adjoint_mix_kernel(const float *__restric
 #pragma unroll
     for (int v = 0; v < 4; ++v) part[wave][(4 * kq + v) * 16 + (lane & 15)] = acc[v];
     __syncthreads();
-    const int r = tid >> 4, c = tid & 15;
-    const int kr = tm * 16 + r, kc = tn * 16 + c;
-    if (kr < K && kc < K)
-        gP[(size_t)kr * K + kc] = ((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid];
+    if (tid < 256) {
+        const int r = tid >> 4, c = tid & 15;
+        const int kr = tm * 16 + r, kc = tn * 16 + c;
+        float sum = part[0][tid];
+#pragma unroll
+        for (int w = 1; w < MIX_WAVES; ++w) sum += part[w][tid];
+        if (kr < K && kc < K) gP[(size_t)kr * K + kc] = sum;
+    }
 }
 
 hipError_t launch_adjoint_mix(const float *nu, int ldn, const float *V, int K, int S,
@@ -1143,9 +1149,9 @@ hipError_t launch_adjoint_mix(const float *nu, int ldn, const float *V, int K, i
     const int nt = (K + 15) / 16;
     const int nG = nt * nt;
     const int tiles = nt * ((S + 15) / 16);
-    const int nB = (tiles + 3) / 4;
-    hipLaunchKernelGGL(adjoint_mix_kernel, dim3(nG + nB), dim3(256), 0, stream, nu, ldn, V, K, S,
-                       Pt, gP, mu, ldm, nG);
+    const int nB = (tiles + MIX_WAVES - 1) / MIX_WAVES;
+    hipLaunchKernelGGL(adjoint_mix_kernel, dim3(nG + nB), dim3(64 * MIX_WAVES), 0, stream, nu,
+                       ldn, V, K, S, Pt, gP, mu, ldm, nG);
     return hipGetLastError();
 }
 
