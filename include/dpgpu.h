@@ -54,7 +54,7 @@ extern "C" {
 #define DP_EBADPROB -2   /* transition rows not stochastic (only with DP_VALIDATE)       */
 #define DP_ENOWS    -3   /* workspace missing or smaller than the *_workspace_bytes()    */
 #define DP_EHIP     -4   /* a HIP runtime call failed                                    */
-#define DP_ETIMEOUT -5   /* a persistent kernel's bounded wait expired                   */
+#define DP_ETIMEOUT -5   /* reserved (no call of this version returns it)                 */
 #define DP_ENOMEM   -6   /* host allocation failed (plans only)                          */
 #define DP_ENOTSUP  -7   /* valid request outside what this build supports               */
 
@@ -97,7 +97,8 @@ const char *dp_last_error(void);
  * R outputs per lane, D moves per chunk, NW waves per block, NSPLIT blocks of the move
  * range (NW % NSPLIT == 0).  R = 0 restores the built-in choice.  The shape never changes
  * results: every shape yields bitwise the same values and policies.  DP_EINVAL for a
- * shape this build has no kernel for.  Not thread-safe with concurrent solves. */
+ * shape this build has no kernel for; a later solve whose move window does not fit the
+ * forced shape's LDS returns DP_ENOTSUP.  Not thread-safe with concurrent solves. */
 int dp_set_sweep_shape(int R, int D, int NW, int NSPLIT);
 
 /* Measurement hook: while on (1, or 2 for events created without the system-scope
@@ -124,7 +125,11 @@ size_t dp_ckpt_bytes(const dp_problem *pb);
  *   V       out: [T+1][K][S] (DP_STORE_V_ALL; slice T is v_term) or [K][S] (V_1 only)
  *   policy  out: [T][K][S] int16 next-state index j, or NULL
  *   ckpt    out: dp_ckpt_bytes(pb) bytes for a later dp_adjoint, or NULL
- *   ws      workspace of at least dp_workspace_bytes(pb) bytes, 256-byte aligned */
+ *   ws      workspace of at least dp_workspace_bytes(pb) bytes, 256-byte aligned
+ * Errors (all checked on the host before any device work, except DP_EBADPROB and DP_EHIP):
+ * DP_EINVAL (bad dimension, parameter or pointer), DP_ENOWS, DP_ENOTSUP (a move window
+ * w_up + w_down + 1 wider than the LDS of any sweep tile holds, about 19,800 moves),
+ * DP_EBADPROB (DP_VALIDATE found a bad row of P), DP_EHIP. */
 int dp_solve(const dp_problem *pb, const float *lam, const float *P, const float *v_term,
              float *V, int16_t *policy, void *ckpt, void *ws, size_t ws_bytes, void *stream);
 

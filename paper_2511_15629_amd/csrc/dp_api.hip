@@ -240,7 +240,7 @@ const char *dp_strerror(int code)
     case DP_EBADPROB: return "transition rows are not stochastic";
     case DP_ENOWS: return "workspace missing or too small";
     case DP_EHIP: return "HIP runtime error";
-    case DP_ETIMEOUT: return "persistent kernel wait timed out";
+    case DP_ETIMEOUT: return "reserved error code";
     case DP_ENOMEM: return "host allocation failed";
     case DP_ENOTSUP: return "not supported by this build";
     default: return "unknown error";
