@@ -53,7 +53,8 @@ int span_bucket(int span)
 
 bool shape_fits(const dpk::SweepShape &sh, int w_up, int w_down)
 {
-    return dpk::sweep_lds_bytes(sh, w_up, w_down) <= 160 * 1024;
+    const size_t tile = (dpk::sweep_lds_bytes(sh, w_up, w_down) + 15) & ~(size_t)15;
+    return tile * dpk::batched_tiles_per_block(sh) <= 160 * 1024;
 }
 
 std::string shape_str(const dpk::SweepShape &sh)

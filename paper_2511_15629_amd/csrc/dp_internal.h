@@ -61,6 +61,9 @@ hipError_t launch_batched_contract(const BatchDesc *desc, const ContractItem *it
 int panel_class(int K);
 hipError_t launch_batched_panel(const BatchDesc *desc, const ContractItem *items, int n, int tau,
                                 int kmax, hipStream_t stream);
+// Sweep tiles per block in batched launches (four for one-wave shapes, else one); the
+// block's LDS is that many 16-byte aligned copies of sweep_lds_bytes.
+int batched_tiles_per_block(const SweepShape &sh);
 hipError_t launch_batched_sweep(const BatchDesc *desc, const SweepItem *items, int n, int tau,
                                 const SweepShape &sh, size_t lds, hipStream_t stream);
 

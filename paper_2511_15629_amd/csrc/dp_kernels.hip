@@ -184,13 +184,24 @@ hipError_t launch_contract(const float *A, bool transA, const float *B, int ldb,
 // from the same operands, so the equality is exact, and "first chunk, then first move
 // within it" is the smallest next state attaining the maximum.
 // ------------------------------------------------------------------------------------
+// Barrier between a tile's LDS phases: the block's, or for a one-wave tile only a code
+// motion fence (one wave's LDS operations complete in program order).
+template <int NW>
+__device__ __forceinline__ void sweep_sync()
+{
+    if constexpr (NW == 1)
+        __builtin_amdgcn_wave_barrier();
+    else
+        __syncthreads();
+}
+
+// smem: this tile's LDS (sweep_lds_bytes); tid: thread index within the tile's NW waves.
 template <int R, int D, int NW, int NSPLIT>
-__device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, const int tile)
+__device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, const int tile,
+                                            float *smem, const int tid)
 {
     constexpr int NS = NW / NSPLIT;
     constexpr int TS = 64 * R * NS;
-    extern __shared__ float4 smem4[];
-    float *smem = reinterpret_cast<float *>(smem4);
 
     const int s0 = tile * TS;
     const int S = a.S;
@@ -206,7 +217,6 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
     float *pb = rl + nrl;
     int *pc = reinterpret_cast<int *>(pb + NSPLIT * TS);
 
-    const int tid = threadIdx.x;
     const float NEG = -INFINITY;
     // Every global value the block needs is requested before any is waited for, so the
     // block pays one memory round trip rather than one per dependent load: the W row over
@@ -239,7 +249,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
         const int d = dlo + i;
         rl[i] = (d <= dhi) ? move_reward(lam, d, a.pay) : NEG;
     }
-    __syncthreads();
+    sweep_sync<NW>();
 
     const int wave = tid >> 6, lane = tid & 63;
     const int ws = wave % NS, wsp = wave / NS;
@@ -289,7 +299,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
         pb[wsp * TS + base + i] = best[i];
         pc[wsp * TS + base + i] = cid[i];
     }
-    __syncthreads();
+    sweep_sync<NW>();
 
     const double Ct = off_next + (double)shift;   // shift = W_t[0][0], the normalisation
     for (int o = tid; o < TS; o += NW * 64) {
@@ -315,9 +325,10 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
         const float vn = bv - shift;
         const size_t idx = (size_t)k * S + s;
         a.vnorm[(size_t)k * a.ldv + s] = vn;
-        if (a.vabs) a.vabs[idx] = (float)((double)vn + Ct);
-        if (a.pol) a.pol[idx] = (int16_t)j;
-        if (a.ckpt_v) a.ckpt_v[idx] = vn;
+        // outputs the next launch does not read go out as non-temporal stores
+        if (a.vabs) __builtin_nontemporal_store((float)((double)vn + Ct), &a.vabs[idx]);
+        if (a.pol) __builtin_nontemporal_store((int16_t)j, &a.pol[idx]);
+        if (a.ckpt_v) __builtin_nontemporal_store(vn, &a.ckpt_v[idx]);
     }
     if (k == 0 && tile == 0 && tid == 0) {
         a.off_cur[0] = Ct;
@@ -328,7 +339,9 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
 template <int R, int D, int NW, int NSPLIT>
 __global__ __launch_bounds__(NW * 64) void sweep_kernel(SweepArgs a)
 {
-    sweep_block<R, D, NW, NSPLIT>(a, blockIdx.y, blockIdx.x);
+    extern __shared__ float4 smem4[];
+    sweep_block<R, D, NW, NSPLIT>(a, blockIdx.y, blockIdx.x, reinterpret_cast<float *>(smem4),
+                                  threadIdx.x);
 }
 
 int sweep_tile(const SweepShape &sh) { return 64 * sh.R * (sh.NW / sh.NSPLIT); }
@@ -698,12 +711,24 @@ hipError_t launch_iid_stage(const IidArgs &a_in, hipStream_t stream)
 // is at its own stage t = T_i - tau + 1 (inactive once t < 1).  The same tile functions
 // as the single solve, with arguments taken from the instance descriptor.
 // ------------------------------------------------------------------------------------
+// One-wave shapes run four independent tiles per block (one per wave, each with its own
+// LDS slice of lds_tile floats), so a CU keeps four times as many short tiles in flight.
+template <int NW>
+constexpr int tiles_per_block() { return NW == 1 ? 4 : 1; }
+
 template <int R, int D, int NW, int NSPLIT>
-__global__ __launch_bounds__(NW * 64) void batched_sweep_kernel(const BatchDesc *__restrict__ desc,
-                                                                const SweepItem *__restrict__ items,
-                                                                int tau)
+__global__ __launch_bounds__(NW * 64 * tiles_per_block<NW>()) void batched_sweep_kernel(
+    const BatchDesc *__restrict__ desc, const SweepItem *__restrict__ items, int n, int tau,
+    int lds_tile)
 {
-    const SweepItem it = items[blockIdx.x];
+    extern __shared__ float4 smem4[];
+    constexpr int TPB = tiles_per_block<NW>();
+    // the wave's slot is uniform across its lanes; readfirstlane lets the compiler keep the
+    // item, its descriptor and every derived address in scalar registers
+    const int slot = TPB > 1 ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) : 0;
+    const int item = blockIdx.x * TPB + slot;
+    if (item >= n) return;                 // per wave when TPB > 1 (no block barrier then)
+    const SweepItem it = items[item];
     const BatchDesc d = desc[it.inst];
     const int t = d.T - tau + 1;
     if (t < 1) return;
@@ -725,7 +750,9 @@ __global__ __launch_bounds__(NW * 64) void batched_sweep_kernel(const BatchDesc 
     a.pol = d.pol ? d.pol + (size_t)(t - 1) * d.K * d.S : nullptr;
     a.ckpt_v = nullptr;
     a.ckpt_off = nullptr;
-    sweep_block<R, D, NW, NSPLIT>(a, it.k, it.tile);
+    sweep_block<R, D, NW, NSPLIT>(a, it.k, it.tile,
+                                  reinterpret_cast<float *>(smem4) + (size_t)slot * lds_tile,
+                                  TPB > 1 ? (int)(threadIdx.x & 63) : (int)threadIdx.x);
 }
 
 __global__ __launch_bounds__(256) void batched_contract_kernel(const BatchDesc *__restrict__ desc,
@@ -949,13 +976,20 @@ hipError_t launch_batched_contract(const BatchDesc *desc, const ContractItem *it
     return hipGetLastError();
 }
 
+int batched_tiles_per_block(const SweepShape &sh) { return sh.NW == 1 ? tiles_per_block<1>() : 1; }
+
 hipError_t launch_batched_sweep(const BatchDesc *desc, const SweepItem *items, int n, int tau,
                                 const SweepShape &sh, size_t lds, hipStream_t stream)
 {
+    // lds: one tile's bytes; a block of tiles_per_block tiles gets one 16-byte aligned
+    // slice each
+    const int lds_tile = (int)(((lds + 15) & ~(size_t)15) / sizeof(float));
 #define X(r, d, nw, ns)                                                                      \
     if (sh.R == r && sh.D == d && sh.NW == nw && sh.NSPLIT == ns) {                          \
-        hipLaunchKernelGGL((batched_sweep_kernel<r, d, nw, ns>), dim3(n), dim3(nw * 64), lds, \
-                           stream, desc, items, tau);                                        \
+        constexpr int tpb = tiles_per_block<nw>();                                           \
+        hipLaunchKernelGGL((batched_sweep_kernel<r, d, nw, ns>), dim3((n + tpb - 1) / tpb),  \
+                           dim3(nw * 64 * tpb), (size_t)lds_tile * sizeof(float) * tpb,      \
+                           stream, desc, items, n, tau, lds_tile);                           \
         return hipGetLastError();                                                            \
     }
     DP_SWEEP_SHAPES(X)
