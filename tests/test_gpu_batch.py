@@ -83,6 +83,35 @@ def test_replay_with_new_pointers_and_data(dp):
     plan.close()
 
 
+def test_repeated_replays_match_eager_each_time(dp):
+    # the captured graph is replayed several times, alternating two price sets, with the
+    # program's own eager work and synchronisations between replays; every replay must
+    # equal the eager solve of its data
+    insts = small_batch()[:6]
+    plan = dp.BatchPlan([(i.T, i.K, i.storage) for i in insts])
+    rng = np.random.default_rng(11)
+    sets = [[i.lam for i in insts],
+            [wl.f32(i.lam.astype(np.float64) + rng.normal(0, 15, i.lam.shape)) for i in insts]]
+    eager = []
+    for lams in sets:
+        outs = []
+        for n, inst in enumerate(insts):
+            o = dp.solve(dev(lams[n]), dev(inst.P), inst.storage, store_all=False, policy=True)
+            outs.append((o["V"].clone(), o["policy"].clone()))
+        torch.cuda.synchronize()
+        eager.append(outs)
+    for rep in range(4):
+        which = rep % 2
+        Vb, pb = run_batch(dp, plan, insts, lam_override=sets[which])
+        junk = torch.randn(1 << 16, device="cuda").sum()        # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.isfinite(junk)
+        for n, inst in enumerate(insts):
+            assert torch.equal(Vb[n], eager[which][n][0]), (rep, inst.name)
+            assert torch.equal(pb[n], eager[which][n][1]), (rep, inst.name)
+    plan.close()
+
+
 def test_autotuned_plan_is_bitwise_equal_and_cache_is_reused(dp, tmp_path):
     insts = small_batch()
     cache = str(tmp_path / "tune.txt")
