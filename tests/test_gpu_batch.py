@@ -83,6 +83,23 @@ def test_replay_with_new_pointers_and_data(dp):
     plan.close()
 
 
+def test_large_chains_use_strips_and_equal_looped(dp):
+    # K > 128 takes the 64-column strip expectation, K <= 128 the LDS panels; mixed in one plan
+    specs = [(21, 4, 130, 300, 20, 25, {}), (22, 3, 200, 150, 9, 7, dict(c_start=1.0)),
+             (23, 5, 100, 257, 40, 40, {}), (24, 4, 129, 64, 3, 5, {})]
+    insts = [wl.random_small(sd, T, K, S, wu, wd, **kw) for (sd, T, K, S, wu, wd, kw) in specs]
+    plan = dp.BatchPlan([(i.T, i.K, i.storage) for i in insts])
+    text = plan.describe()
+    assert "strips" in text and " 0 strips" not in text, text
+    Vb, pb = run_batch(dp, plan, insts)
+    Vl, pl = run_batch(dp, plan, insts, looped=True)
+    for n, inst in enumerate(insts):
+        assert torch.equal(Vb[n], Vl[n]) and torch.equal(pb[n], pl[n]), inst.name
+        ref = oracle.solve(inst.storage, inst.lam, inst.P, keep_all=False, want_policy=False)
+        assert value_error(Vb[n].cpu().numpy(), ref["V1"]) <= RTOL, inst.name
+    plan.close()
+
+
 def test_repeated_replays_match_eager_each_time(dp):
     # the captured graph is replayed several times, alternating two price sets, with the
     # program's own eager work and synchronisations between replays; every replay must
