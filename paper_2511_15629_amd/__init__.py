@@ -38,6 +38,31 @@ def _dev_f32(x, name):
     return x.contiguous()
 
 
+def _check(x, name, shape, dtype, device):
+    """The library trusts sizes: every array it reads or writes is checked here."""
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if x.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+    if x.device != device:
+        raise ValueError(f"{name} is on {x.device}, expected {device}")
+    if shape is not None and tuple(x.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(x.shape)}")
+    if not x.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return x
+
+
+def _keep(stream, *tensors):
+    """On a stream other than torch's current one, tell the caching allocator that these
+    buffers are in use there until the queued work ends."""
+    if stream is None:
+        return
+    for t in tensors:
+        if t is not None:
+            t.record_stream(stream)
+
+
 def _workspace(nbytes: int, device) -> torch.Tensor:
     # torch's caching allocator returns blocks aligned to at least 512 bytes
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
@@ -86,6 +111,9 @@ class Solver:
         self.ws = _workspace(nws, dev)
 
     def run(self, v_term: Optional[torch.Tensor] = None, stream=None):
+        if v_term is not None:
+            K, S = self.pb.K, self.pb.st.S
+            _check(v_term, "v_term", (K, S), torch.float32, self.lam.device)
         check(lib().dp_solve(ctypes.byref(self.pb), _ptr(self.lam), _ptr(self.P), _ptr(v_term),
                              _ptr(self.V), _ptr(self.policy), _ptr(self.ckpt), _ptr(self.ws),
                              ctypes.c_size_t(self.ws.numel()), _stream(stream)))
@@ -117,9 +145,10 @@ def solve_independent(lam: torch.Tensor, prob: torch.Tensor, S: int, delta: floa
     """
     lam = _dev_f32(lam, "lam")
     prob = _dev_f32(prob, "prob")
+    if lam.dim() != 2:
+        raise ValueError("lam must be [T, R]")
     T, R = lam.shape
-    if tuple(prob.shape) != (T, R):
-        raise ValueError("prob must have the shape of lam")
+    _check(prob, "prob", (T, R), torch.float32, lam.device)
     pb = _iid_problem(T, R, S, delta, eta, p_bar, store_all)
     L = lib()
     nws = L.dp_iid_workspace_bytes(ctypes.byref(pb))
@@ -131,6 +160,7 @@ def solve_independent(lam: torch.Tensor, prob: torch.Tensor, S: int, delta: floa
     ws = _workspace(nws, dev)
     check(L.dp_solve_iid(ctypes.byref(pb), _ptr(lam), _ptr(prob), _ptr(V), _ptr(pol), _ptr(ws),
                          ctypes.c_size_t(ws.numel()), _stream(stream)))
+    _keep(stream, lam, prob, ws)
     return {"V": V, "policy": pol, "_ws": ws}
 
 
@@ -146,18 +176,17 @@ def solve(lam: torch.Tensor, P: torch.Tensor, storage, v_term: Optional[torch.Te
     """
     lam = _dev_f32(lam, "lam")
     P = _dev_f32(P, "P")
+    if lam.dim() != 2:
+        raise ValueError("lam must be [T, K]")
     T, K = lam.shape
-    if tuple(P.shape) != (T, K, K):
-        raise ValueError(f"P must have shape {(T, K, K)}, got {tuple(P.shape)}")
+    _check(P, "P", (T, K, K), torch.float32, lam.device)
     S = int(storage.S)
     flags = (DP_STORE_V_ALL if store_all else 0) | (DP_VALIDATE if validate else 0)
     pb = make_problem(T, K, storage, flags, ckpt_every)
     L = lib()
     dev = lam.device
     if v_term is not None:
-        v_term = _dev_f32(v_term, "v_term")
-        if tuple(v_term.shape) != (K, S):
-            raise ValueError("v_term must be [K, S]")
+        v_term = _check(_dev_f32(v_term, "v_term"), "v_term", (K, S), torch.float32, dev)
     V = torch.empty((T + 1, K, S) if store_all else (K, S), dtype=torch.float32, device=dev)
     pol = torch.empty((T, K, S), dtype=torch.int16, device=dev) if policy else None
     ck = None
@@ -169,6 +198,7 @@ def solve(lam: torch.Tensor, P: torch.Tensor, storage, v_term: Optional[torch.Te
     ws = _workspace(nws, dev)
     check(L.dp_solve(ctypes.byref(pb), _ptr(lam), _ptr(P), _ptr(v_term), _ptr(V), _ptr(pol),
                      _ptr(ck), _ptr(ws), ctypes.c_size_t(ws.numel()), _stream(stream)))
+    _keep(stream, lam, P, v_term, ws)
     return {"V": V, "policy": pol, "ckpt": ck, "problem": pb, "_ws": ws}
 
 
@@ -178,21 +208,34 @@ def adjoint(lam, P, storage, seed, *, V_all=None, policy=None, ckpt=None, ckpt_e
     lam = _dev_f32(lam, "lam")
     P = _dev_f32(P, "P")
     seed = _dev_f32(seed, "seed")
+    if lam.dim() != 2:
+        raise ValueError("lam must be [T, K]")
     T, K = lam.shape
     S = int(storage.S)
+    dev = lam.device
+    _check(P, "P", (T, K, K), torch.float32, dev)
+    _check(seed, "seed", (K, S), torch.float32, dev)
     pb = make_problem(T, K, storage, 0, ckpt_every if ckpt is not None else 0)
     L = lib()
-    dev = lam.device
+    if ckpt is not None:
+        _check(ckpt, "ckpt", None, torch.uint8, dev)
+        if ckpt.numel() < L.dp_ckpt_bytes(ctypes.byref(pb)):
+            raise ValueError("ckpt is smaller than dp_ckpt_bytes for this problem")
+    if V_all is not None:
+        _check(V_all, "V_all", (T + 1, K, S), torch.float32, dev)
+    if policy is not None:
+        _check(policy, "policy", (T, K, S), torch.int16, dev)
     g_lam = torch.empty((T, K), dtype=torch.float32, device=dev)
     g_P = torch.empty((T, K, K), dtype=torch.float32, device=dev)
     g_v = torch.empty((K, S), dtype=torch.float32, device=dev) if want_vterm else None
     ws = _workspace(L.dp_adjoint_workspace_bytes(ctypes.byref(pb)), dev)
     if v_term is not None:
-        v_term = _dev_f32(v_term, "v_term")
+        v_term = _check(_dev_f32(v_term, "v_term"), "v_term", (K, S), torch.float32, dev)
     check(L.dp_adjoint(ctypes.byref(pb), _ptr(lam), _ptr(P), _ptr(v_term),
                        _ptr(V_all), _ptr(policy), _ptr(ckpt), _ptr(seed), _ptr(g_lam),
                        _ptr(g_P), _ptr(g_v), _ptr(ws), ctypes.c_size_t(ws.numel()),
                        _stream(stream)))
+    _keep(stream, lam, P, seed, v_term, ws)
     return {"grad_lam": g_lam, "grad_P": g_P, "grad_vterm": g_v}
 
 

@@ -36,8 +36,25 @@ class BatchPlan:
             arr[i] = None if t is None else t.data_ptr()
         return arr
 
+    def _check_io(self, lams, Ps, V1s, policies):
+        from . import _check
+        n = len(self.problems)
+        lists = [("lams", lams), ("Ps", Ps), ("V1s", V1s)] + ([("policies", policies)] if policies is not None else [])
+        for name, seq in lists:
+            if len(seq) != n:
+                raise ValueError(f"{name} must hold {n} tensors, got {len(seq)}")
+        dev = lams[0].device
+        for i, pb in enumerate(self.problems):
+            T, K, S = pb.T, pb.K, pb.st.S
+            _check(lams[i], f"lams[{i}]", (T, K), torch.float32, dev)
+            _check(Ps[i], f"Ps[{i}]", (T, K, K), torch.float32, dev)
+            _check(V1s[i], f"V1s[{i}]", (K, S), torch.float32, dev)
+            if policies is not None:
+                _check(policies[i], f"policies[{i}]", (T, K, S), torch.int16, dev)
+
     def solve(self, lams: List[torch.Tensor], Ps: List[torch.Tensor], V1s: List[torch.Tensor],
               policies=None, *, looped: bool = False, stream=None):
+        self._check_io(lams, Ps, V1s, policies)
         s = stream if stream is not None else torch.cuda.current_stream()
         f = lib().dp_batch_solve_looped if looped else lib().dp_batch_solve
         pol = self._ptrs(policies) if policies is not None else None

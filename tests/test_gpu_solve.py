@@ -168,3 +168,24 @@ def test_validation_rejects_non_stochastic_rows(dp):
     assert e.value.code == -2
     dp.solve(dev(inst.lam), dev(inst.P), inst.storage, validate=True)
     torch.cuda.synchronize()
+
+
+def test_binding_checks_shapes_before_queueing(dp):
+    inst = wl.random_small(61, 4, 3, 20, 2, 3)
+    lam, P = dev(inst.lam), dev(inst.P)
+    out = gpu_solve(dp, inst, store_all=True)
+    seed = torch.zeros(3, 20, device="cuda")
+    with pytest.raises(ValueError):
+        dp.adjoint(lam, P, inst.storage, seed, V_all=out["V"][:-1], policy=out["policy"])
+    with pytest.raises(TypeError):
+        dp.adjoint(lam, P, inst.storage, seed, V_all=out["V"], policy=out["policy"].int())
+    with pytest.raises(ValueError):
+        dp.solve(lam, P[:, :2, :], inst.storage)
+    with pytest.raises(ValueError):
+        dp.solve(lam, P, inst.storage, v_term=torch.zeros(3, 19, device="cuda"))
+    plan = dp.BatchPlan([(inst.T, inst.K, inst.storage)])
+    with pytest.raises(ValueError):
+        plan.solve([lam], [P], [torch.empty(3, 21, device="cuda")])
+    with pytest.raises(ValueError):
+        plan.solve([lam, lam], [P], [torch.empty(3, 20, device="cuda")])
+    plan.close()
