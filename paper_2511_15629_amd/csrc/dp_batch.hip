@@ -34,11 +34,18 @@ const dpk::SweepShape kCandidates[] = {
     {4, 4, 1, 1},
 };
 
+// Instances fall into independent groups by expectation kernel: panel classes 0..2
+// (K <= 32, <= 64, <= 128) and strips (K > 128).  Each group is one branch of the graph.
+constexpr int NGROUPS = 4;
+
+int expectation_group(int K) { return K <= 128 ? dpk::panel_class(K) : 3; }
+
 struct TileClass {
     dpk::SweepShape sh;
     int span_lo, span_hi;
     std::vector<int> inst;
-    std::vector<dpk::SweepItem> items;
+    std::vector<dpk::SweepItem> items;      // ordered by group, then heavier instances first
+    int goff[NGROUPS] = {0, 0, 0, 0}, gn[NGROUPS] = {0, 0, 0, 0};
     dpk::SweepItem *d_items = nullptr;
     size_t lds = 0;
     double tuned_us = -1.0;
@@ -83,6 +90,8 @@ struct dp_batch_plan {
     char *ws = nullptr;
     size_t ws_bytes = 0;
     hipStream_t cap = nullptr;
+    hipStream_t branch[NGROUPS] = {};      // capture streams of the graph's group branches
+    hipEvent_t fork = nullptr, join[NGROUPS] = {};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t staged = nullptr;
@@ -104,32 +113,69 @@ static void destroy_plan(dp_batch_plan *p)
     if (p->hstage) (void)hipHostFree(p->hstage);
     if (p->ws) (void)hipFree(p->ws);
     if (p->staged) (void)hipEventDestroy(p->staged);
+    if (p->fork) (void)hipEventDestroy(p->fork);
+    for (int g = 0; g < NGROUPS; ++g) {
+        if (p->join[g]) (void)hipEventDestroy(p->join[g]);
+        if (p->branch[g]) (void)hipStreamDestroy(p->branch[g]);
+    }
     if (p->cap) (void)hipStreamDestroy(p->cap);
     delete p;
 }
 
-// Launch one whole batched solve (init + all stages) on `s`.
-static int enqueue_all(dp_batch_plan *p, hipStream_t s)
+// The stages of one instance group on stream s: per batch stage its expectation launch,
+// then its share of every sweep class.
+static int enqueue_group(dp_batch_plan *p, int g, hipStream_t s)
 {
-    hipError_t e = dpk::launch_batched_init(p->ddesc, p->n, s);
-    if (e != hipSuccess) return hip_fail(e, "batched init");
+    hipError_t e = hipSuccess;
     for (int tau = 1; tau <= p->Tmax; ++tau) {
-        for (int c = 0; c < 3; ++c) {
-            if (!p->pan_n[c]) continue;
-            e = dpk::launch_batched_panel(p->ddesc, p->d_pitems + p->pan_off[c], p->pan_n[c], tau,
-                                          p->pan_kmax[c], s);
+        if (g < 3 && p->pan_n[g]) {
+            e = dpk::launch_batched_panel(p->ddesc, p->d_pitems + p->pan_off[g], p->pan_n[g], tau,
+                                          p->pan_kmax[g], s);
             if (e != hipSuccess) return hip_fail(e, "batched expectation (panels)");
         }
-        if (p->n_citems) {
+        if (g == 3 && p->n_citems) {
             e = dpk::launch_batched_contract(p->ddesc, p->d_citems, p->n_citems, tau, s);
             if (e != hipSuccess) return hip_fail(e, "batched expectation (strips)");
         }
         for (auto &c : p->classes) {
-            if (c.items.empty()) continue;
-            e = dpk::launch_batched_sweep(p->ddesc, c.d_items, (int)c.items.size(), tau, c.sh,
+            if (!c.gn[g]) continue;
+            e = dpk::launch_batched_sweep(p->ddesc, c.d_items + c.goff[g], c.gn[g], tau, c.sh,
                                           c.lds, s);
             if (e != hipSuccess) return hip_fail(e, "batched sweep");
         }
+    }
+    return DP_OK;
+}
+
+static bool group_used(const dp_batch_plan *p, int g)
+{
+    if (g < 3 ? p->pan_n[g] > 0 : p->n_citems > 0) return true;
+    for (auto &c : p->classes)
+        if (c.gn[g]) return true;
+    return false;
+}
+
+// Launch one whole batched solve on `s` (the capture stream): the init kernel, then one
+// branch per instance group on its own stream (groups share no data, so the branches run
+// concurrently and fill each other's launch tails), joined back into `s`.
+static int enqueue_all(dp_batch_plan *p, hipStream_t s)
+{
+    hipError_t e = dpk::launch_batched_init(p->ddesc, p->n, s);
+    if (e != hipSuccess) return hip_fail(e, "batched init");
+    e = hipEventRecord(p->fork, s);
+    if (e != hipSuccess) return hip_fail(e, "fork");
+    bool first = true;
+    for (int g = 0; g < NGROUPS; ++g) {
+        if (!group_used(p, g)) continue;
+        hipStream_t sg = first ? s : p->branch[g];
+        if (!first && (e = hipStreamWaitEvent(sg, p->fork, 0)) != hipSuccess) return hip_fail(e, "fork");
+        int rc = enqueue_group(p, g, sg);
+        if (rc != DP_OK) return rc;
+        if (!first) {
+            if ((e = hipEventRecord(p->join[g], sg)) != hipSuccess) return hip_fail(e, "join");
+            if ((e = hipStreamWaitEvent(s, p->join[g], 0)) != hipSuccess) return hip_fail(e, "join");
+        }
+        first = false;
     }
     return DP_OK;
 }
@@ -139,17 +185,24 @@ static int build_items(dp_batch_plan *p, TileClass &c)
     c.items.clear();
     c.lds = 0;
     const int TS = dpk::sweep_tile(c.sh);
-    // heavier instances (wider spans, more outputs) first, for a short tail
+    // by instance group (a contiguous range per group), then heavier instances (wider
+    // spans, more outputs) first, for a short tail
     std::vector<int> order = c.inst;
     std::sort(order.begin(), order.end(), [&](int a, int b) {
+        const int ga = expectation_group(p->probs[a].K), gb = expectation_group(p->probs[b].K);
+        if (ga != gb) return ga < gb;
         const auto &x = p->probs[a].st, &y = p->probs[b].st;
         return (long)(x.w_up + x.w_down) * p->probs[a].K > (long)(y.w_up + y.w_down) * p->probs[b].K;
     });
+    for (int g = 0; g < NGROUPS; ++g) c.gn[g] = 0;
     for (int i : order) {
         const dp_problem &pb = p->probs[i];
+        const int g = expectation_group(pb.K);
+        if (c.gn[g] == 0) c.goff[g] = (int)c.items.size();
         const int tiles = (pb.st.S + TS - 1) / TS;
         for (int k = 0; k < pb.K; ++k)
             for (int tl = 0; tl < tiles; ++tl) c.items.push_back({i, k, tl});
+        c.gn[g] = (int)c.items.size() - c.goff[g];
         c.lds = std::max(c.lds, dpk::sweep_lds_bytes(c.sh, pb.st.w_up, pb.st.w_down));
     }
     if (c.d_items) {
@@ -292,6 +345,11 @@ int dp_batch_plan_create(dp_batch_plan **out, int n, const dp_problem *probs,
     if (e == hipSuccess) e = hipHostMalloc(&p->hstage, sizeof(dpk::BatchDesc) * n);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&p->staged, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming);
+    for (int g = 0; g < NGROUPS && e == hipSuccess; ++g) {
+        e = hipStreamCreateWithFlags(&p->branch[g], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->join[g], hipEventDisableTiming);
+    }
     if (e != hipSuccess) {
         destroy_plan(p);
         return hip_fail(e, "plan allocation");
