@@ -23,6 +23,7 @@ import argparse
 import json
 import os
 import sys
+import threading
 import time
 
 # Peak of the sweep: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 3.93e13 VALU lane-instructions/s;
@@ -38,11 +39,70 @@ def host_cores() -> int:
         return os.cpu_count() or 1
 
 
-def timed_solves(dp, torch, inst, steps, warmup):
+class ClockSampler:
+    """The GPU's current graphics clock level (MHz), read from the driver's
+    pp_dpm_sclk table (the line marked '*') of the card at the device's PCI address,
+    every few ms on a thread while a `with` block runs."""
+
+    def __init__(self, torch, period_s=0.004):
+        self.period, self.samples, self.path = period_s, [], None
+        self._stop = threading.Event()
+        try:
+            pr = torch.cuda.get_device_properties(0)
+            bdf = f"{pr.pci_domain_id:04x}:{pr.pci_bus_id:02x}:{pr.pci_device_id:02x}.0"
+            for card in sorted(os.listdir("/sys/class/drm")):
+                dev = os.path.join("/sys/class/drm", card, "device")
+                f = os.path.join(dev, "pp_dpm_sclk")
+                if card.startswith("card") and os.path.exists(f) and \
+                        os.path.basename(os.path.realpath(dev)) == bdf:
+                    self.path = f
+                    break
+        except Exception:
+            self.path = None
+
+    def _read(self):
+        with open(self.path) as fh:
+            for line in fh:
+                if line.rstrip().endswith("*"):
+                    return float(line.split(":")[1].strip().lower().split("mhz")[0])
+        return None
+
+    def _run(self):
+        while not self._stop.is_set():
+            try:
+                v = self._read()
+            except Exception:
+                return
+            if v is not None:
+                self.samples.append(v)
+            self._stop.wait(self.period)
+
+    def __enter__(self):
+        self._t = None
+        if self.path:
+            self._t = threading.Thread(target=self._run, daemon=True)
+            self._t.start()
+        return self
+
+    def __exit__(self, *exc):
+        self._stop.set()
+        if self._t is not None:
+            self._t.join()
+
+    def summary(self):
+        if not self.samples:
+            return None
+        v = sorted(self.samples)
+        return {"median": v[len(v) // 2], "min": v[0], "max": v[-1], "samples": len(v),
+                "source": "driver pp_dpm_sclk current level during the event-timed solves"}
+
+
+def timed_solves(dp, torch, inst, steps, warmup, clock=None):
     """Wall time per step over `steps` solves (no instrumentation), then the same number
     of identical solves with HIP event pairs (created without the system-scope fence) on
     the solve's stream around every sweep and expectation launch; event packets between
-    launches slow the steps down, so they are kept out of the timed steps."""
+    launches slow the steps down, so they are kept out of the timed steps.  The clock
+    sampler, if given, runs during the event-timed solves only."""
     lam = torch.from_numpy(inst.lam).cuda()
     P = torch.from_numpy(inst.P).cuda()
     solver = dp.Solver(lam, P, inst.storage, store_all=False, policy=True)
@@ -55,9 +115,11 @@ def timed_solves(dp, torch, inst, steps, warmup):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     dp.lib().dp_set_timing(2)
-    for _ in range(steps):
-        solver.run()
-    torch.cuda.synchronize()
+    import contextlib
+    with clock if clock is not None else contextlib.nullcontext():
+        for _ in range(steps):
+            solver.run()
+        torch.cuda.synchronize()
     timing = dp.kernel_timing()
     dp.kernel_timing(False)
     del solver
@@ -175,16 +237,16 @@ def batch_compare(dp, torch, reps=2):
     cand = sum(i.candidates() for i in insts)
     out = {"instances": len(insts), "candidates": cand, "plan_create_s": round(plan_s, 2),
            "plan": plan.describe().strip().splitlines()}
-    for looped in (False, True):
-        plan.solve(lams, Ps, V1s, pols, looped=looped)
+    for name, kw in (("batched", {}), ("batched_no_graph", dict(graph=False)),
+                     ("looped", dict(looped=True))):
+        plan.solve(lams, Ps, V1s, pols, **kw)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(reps):
-            plan.solve(lams, Ps, V1s, pols, looped=looped)
+            plan.solve(lams, Ps, V1s, pols, **kw)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / reps
-        out["looped" if looped else "batched"] = {"ms": round(dt * 1e3, 2),
-                                                  "Gupd_per_s": round(cand / dt / 1e9, 1)}
+        out[name] = {"ms": round(dt * 1e3, 2), "Gupd_per_s": round(cand / dt / 1e9, 1)}
     out["speedup"] = round(out["looped"]["ms"] / out["batched"]["ms"], 3)
     plan.close()
     return out
@@ -251,9 +313,11 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     inst = wl.WORKLOADS[args.workload]()
-    sec, timing = timed_solves(dp, torch, inst, args.steps, args.warmup)
+    clock = ClockSampler(torch)
+    sec, timing = timed_solves(dp, torch, inst, args.steps, args.warmup, clock)
     cand = inst.candidates()
     st = inst.storage
+    dense = inst.T * inst.K * st.S * (st.w_up + st.w_down + 1)
     line = {
         "metric": "DP state-action updates/s", "value": round(cand / sec, 1), "unit": "updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -263,6 +327,10 @@ def main():
                    "w_up": st.w_up, "w_down": st.w_down, "candidates_per_step": cand,
                    "outputs": "V_1 f32 + all int16 policies", "parallelism": "single GPU"},
         "roofline": roofline_of(inst, timing, measured_traffic(args.workload)),
+        "dense_equivalent": {"updates_per_step": dense, "updates_per_s": round(dense / sec, 1),
+                             "note": "T K S (W_c + W_d + 1): the full window at every level, "
+                                     "as a dense action grid counts it"},
+        "sclk_mhz": clock.summary(),
     }
     if args.copy_probe:
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")

@@ -188,8 +188,10 @@ int dp_solve_iid(const dp_iid_problem *pb, const float *lam, const float *prob, 
 
 /* Batched solves of many independent instances (not in the paper; Sec. V's duration sweeps
  * are such batches).  All instances advance stage-synchronously: batch stage tau puts
- * instance i at its own stage T_i - tau + 1, and each tau is one expectation launch per
- * K class plus one sweep launch per tile class.  A plan owns the device descriptor table,
+ * instance i at its own stage T_i - tau + 1.  Instances are grouped by expectation kernel
+ * (K <= 32, <= 64, <= 128, > 128); each group is one stream of launches (per tau, one
+ * expectation launch, then one sweep launch per tile class that has instances in the
+ * group), and the groups run concurrently.  A plan owns the device descriptor table,
  * the work tables, its device workspace (one solver region per instance) and a HIP graph of
  * the whole launch sequence, captured once at creation; it is created for a fixed list of
  * problems (host array probs[n], flags must be 0, ckpt_every ignored) and replayed with new
@@ -212,6 +214,13 @@ int dp_batch_plan_create(dp_batch_plan **out, int n, const dp_problem *probs,
  * them, since every call rewrites the same descriptor table and workspace. */
 int dp_batch_solve(dp_batch_plan *plan, const float *const *lam, const float *const *P,
                    float *const *V1, int16_t *const *policy, void *stream);
+
+/* The same launches as dp_batch_solve, issued directly instead of replaying the graph:
+ * the group streams are forked from `stream` with events and joined back into it.  For
+ * measuring what the graph saves; results are bitwise those of dp_batch_solve.  The same
+ * ordering rule holds. */
+int dp_batch_solve_eager(dp_batch_plan *plan, const float *const *lam, const float *const *P,
+                         float *const *V1, int16_t *const *policy, void *stream);
 
 /* Same batch, one ordinary dp_solve per instance on the stream (for comparison). */
 int dp_batch_solve_looped(dp_batch_plan *plan, const float *const *lam,

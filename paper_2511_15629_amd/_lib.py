@@ -28,7 +28,7 @@ DP_VALIDATE = 0x2
 EXPORTS = (
     "dp_abi_version", "dp_strerror", "dp_last_error", "dp_workspace_bytes", "dp_ckpt_bytes",
     "dp_solve", "dp_adjoint_workspace_bytes", "dp_adjoint", "dp_batch_plan_create",
-    "dp_batch_solve", "dp_batch_solve_looped", "dp_batch_plan_describe",
+    "dp_batch_solve", "dp_batch_solve_eager", "dp_batch_solve_looped", "dp_batch_plan_describe",
     "dp_batch_plan_destroy", "dp_set_sweep_shape", "dp_set_timing", "dp_get_timing",
     "dp_iid_action_grid", "dp_iid_workspace_bytes", "dp_solve_iid",
 )
@@ -83,6 +83,7 @@ def lib():
             "dp_adjoint": ([PP, p, p, p, p, p, p, p, p, p, p, p, sz, p], i),
             "dp_batch_plan_create": ([ctypes.POINTER(p), i, PP, ctypes.c_char_p, p], i),
             "dp_batch_solve": ([p, p, p, p, p, p], i),
+            "dp_batch_solve_eager": ([p, p, p, p, p, p], i),
             "dp_batch_solve_looped": ([p, p, p, p, p, p], i),
             "dp_batch_plan_describe": ([p, ctypes.c_char_p, sz], i),
             "dp_batch_plan_destroy": ([p], None),

@@ -53,10 +53,15 @@ class BatchPlan:
                 _check(policies[i], f"policies[{i}]", (T, K, S), torch.int16, dev)
 
     def solve(self, lams: List[torch.Tensor], Ps: List[torch.Tensor], V1s: List[torch.Tensor],
-              policies=None, *, looped: bool = False, stream=None):
+              policies=None, *, looped: bool = False, graph: bool = True, stream=None):
+        """Batched solve (graph replay); graph=False issues the same launches directly;
+        looped=True runs one dp_solve per instance instead."""
         self._check_io(lams, Ps, V1s, policies)
         s = stream if stream is not None else torch.cuda.current_stream()
-        f = lib().dp_batch_solve_looped if looped else lib().dp_batch_solve
+        if looped:
+            f = lib().dp_batch_solve_looped
+        else:
+            f = lib().dp_batch_solve if graph else lib().dp_batch_solve_eager
         pol = self._ptrs(policies) if policies is not None else None
         check(f(self._h, self._ptrs(lams), self._ptrs(Ps), self._ptrs(V1s), pol,
                 ctypes.c_void_p(s.cuda_stream)))

@@ -519,12 +519,10 @@ static int check_ptrs(dp_batch_plan *p, const float *const *lam, const float *co
     return DP_OK;
 }
 
-int dp_batch_solve(dp_batch_plan *p, const float *const *lam, const float *const *P,
-                   float *const *V1, int16_t *const *policy, void *stream_)
+// Copy the call's pointers into the device descriptor table (pinned staging, async on s).
+static int upload_descriptors(dp_batch_plan *p, const float *const *lam, const float *const *P,
+                              float *const *V1, int16_t *const *policy, hipStream_t s)
 {
-    int rc = check_ptrs(p, lam, P, V1, policy);
-    if (rc != DP_OK) return rc;
-    hipStream_t s = static_cast<hipStream_t>(stream_);
     hipError_t e = hipSuccess;
     if (p->staged_pending) e = hipEventSynchronize(p->staged);   // staging buffer free again
     if (e != hipSuccess) return hip_fail(e, "staging wait");
@@ -539,9 +537,31 @@ int dp_batch_solve(dp_batch_plan *p, const float *const *lam, const float *const
     if (e == hipSuccess) e = hipEventRecord(p->staged, s);
     if (e != hipSuccess) return hip_fail(e, "descriptor upload");
     p->staged_pending = true;
-    e = hipGraphLaunch(p->exec, s);
+    return DP_OK;
+}
+
+int dp_batch_solve(dp_batch_plan *p, const float *const *lam, const float *const *P,
+                   float *const *V1, int16_t *const *policy, void *stream_)
+{
+    int rc = check_ptrs(p, lam, P, V1, policy);
+    if (rc != DP_OK) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream_);
+    rc = upload_descriptors(p, lam, P, V1, policy, s);
+    if (rc != DP_OK) return rc;
+    hipError_t e = hipGraphLaunch(p->exec, s);
     if (e != hipSuccess) return hip_fail(e, "graph launch");
     return DP_OK;
+}
+
+int dp_batch_solve_eager(dp_batch_plan *p, const float *const *lam, const float *const *P,
+                         float *const *V1, int16_t *const *policy, void *stream_)
+{
+    int rc = check_ptrs(p, lam, P, V1, policy);
+    if (rc != DP_OK) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream_);
+    rc = upload_descriptors(p, lam, P, V1, policy, s);
+    if (rc != DP_OK) return rc;
+    return enqueue_all(p, s);
 }
 
 int dp_batch_solve_looped(dp_batch_plan *p, const float *const *lam, const float *const *P,

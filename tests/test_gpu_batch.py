@@ -39,12 +39,12 @@ def small_batch():
     return [wl.random_small(sd, T, K, S, wu, wd, **kw) for (sd, T, K, S, wu, wd, kw) in specs]
 
 
-def run_batch(dp, plan, insts, looped=False, lam_override=None):
+def run_batch(dp, plan, insts, looped=False, lam_override=None, graph=True):
     lams = [dev(i.lam if lam_override is None else lam_override[n]) for n, i in enumerate(insts)]
     Ps = [dev(i.P) for i in insts]
     V1 = [torch.full((i.K, i.storage.S), float("nan"), device="cuda") for i in insts]
     pol = [torch.full((i.T, i.K, i.storage.S), -1, dtype=torch.int16, device="cuda") for i in insts]
-    plan.solve(lams, Ps, V1, pol, looped=looped)
+    plan.solve(lams, Ps, V1, pol, looped=looped, graph=graph)
     torch.cuda.synchronize()
     return V1, pol
 
@@ -80,6 +80,24 @@ def test_replay_with_new_pointers_and_data(dp):
         out = dp.solve(dev(lam2[n]), dev(inst.P), inst.storage, store_all=False, policy=True)
         torch.cuda.synchronize()
         assert torch.equal(Vb[n], out["V"]) and torch.equal(pb[n], out["policy"])
+    plan.close()
+
+
+def test_eager_launches_equal_graph_replay(dp):
+    # every expectation group (K <= 32, <= 64, <= 128, > 128) present, so all four branches
+    # are forked and joined; the eager path issues the captured launches directly
+    specs = [(31, 5, 7, 120, 6, 9, {}), (32, 4, 40, 300, 25, 20, {}), (33, 6, 90, 260, 40, 35, {}),
+             (34, 3, 140, 200, 12, 10, dict(c_start=1.0)), (35, 5, 20, 700, 80, 60, {})]
+    insts = [wl.random_small(sd, T, K, S, wu, wd, **kw) for (sd, T, K, S, wu, wd, kw) in specs]
+    plan = dp.BatchPlan([(i.T, i.K, i.storage) for i in insts])
+    Vg, pg = run_batch(dp, plan, insts)
+    for rep in range(2):
+        Ve, pe = run_batch(dp, plan, insts, graph=False)
+        for n, inst in enumerate(insts):
+            assert torch.equal(Vg[n], Ve[n]) and torch.equal(pg[n], pe[n]), (inst.name, rep)
+    Vl, pl = run_batch(dp, plan, insts, looped=True)
+    for n, inst in enumerate(insts):
+        assert torch.equal(Vg[n], Vl[n]) and torch.equal(pg[n], pl[n]), inst.name
     plan.close()
 
 
