@@ -350,7 +350,7 @@ int dp_solve(const dp_problem *pb, const float *lam, const float *P, const float
 // Adjoint.
 // ------------------------------------------------------------------------------------
 struct AdjLayout {
-    int Spad;
+    int Spad, G;            // G: stages per grad_P launch (nu_t planes kept for a group)
     size_t mu, nu, scale, vseg, polseg, solve_ws, total;
 };
 
@@ -360,8 +360,13 @@ static AdjLayout adj_layout(const dp_problem *pb, bool ckpt_mode)
     L.Spad = pad64(pb->st.S);
     const size_t plane = align256(sizeof(float) * (size_t)pb->K * L.Spad);
     size_t o = 0;
+    // grad_P_t needs nu_t only, off the stage-to-stage path: nu_t of G consecutive stages
+    // are kept and their grad_P computed in one launch (G <= 16, <= 256 MB of planes)
+    L.G = 16;
+    while (L.G > 1 && (size_t)L.G * plane > ((size_t)256 << 20)) L.G >>= 1;
+    if (L.G > pb->T) L.G = pb->T;
     L.mu = o; o += plane;
-    L.nu = o; o += plane;
+    L.nu = o; o += (size_t)L.G * plane;
     L.scale = o; o += 256;
     if (ckpt_mode) {
         const int E = pb->ckpt_every > 0 ? pb->ckpt_every : 16;
@@ -404,6 +409,7 @@ int dp_adjoint(const dp_problem *pb, const float *lam, const float *P, const flo
     char *base = static_cast<char *>(ws);
     float *mu = reinterpret_cast<float *>(base + L.mu);
     float *nu = reinterpret_cast<float *>(base + L.nu);
+    const size_t plane = align256(sizeof(float) * (size_t)K * L.Spad) / sizeof(float);
     const size_t KS = (size_t)K * S;
     const dpk::Payoff pay = {pb->st.delta, pb->st.eta_c, pb->st.eta_d, pb->st.c_deg, pb->st.c_start};
     double *scale = reinterpret_cast<double *>(base + L.scale);
@@ -445,15 +451,22 @@ int dp_adjoint(const dp_problem *pb, const float *lam, const float *P, const flo
             Vseg = V_all + (size_t)(t_lo - 1) * KS;
             pseg = policy + (size_t)(t_lo - 1) * KS;
         }
-        for (int t = t_lo; t <= t_hi; ++t) {
-            const int16_t *pol_t = pseg + (size_t)(t - t_lo) * KS;
-            const float *Vn = Vseg + (size_t)(t + 1 - t_lo) * KS;
-            e = dpk::launch_pushforward(mu, L.Spad, pol_t, K, S, pay, scale, nu, L.Spad,
-                                        grad_lam + (size_t)(t - 1) * K, stream);
-            if (e != hipSuccess) return hip_fail(e, "pushforward");
-            e = dpk::launch_adjoint_mix(nu, L.Spad, Vn, K, S, P + (size_t)(t - 1) * K * K,
-                                        grad_P + (size_t)(t - 1) * K * K, mu, L.Spad, stream);
-            if (e != hipSuccess) return hip_fail(e, "gradP/transport");
+        for (int g0 = t_lo; g0 <= t_hi; g0 += L.G) {
+            const int g1 = g0 + L.G - 1 < t_hi ? g0 + L.G - 1 : t_hi;
+            for (int t = g0; t <= g1; ++t) {
+                const int16_t *pol_t = pseg + (size_t)(t - t_lo) * KS;
+                float *nu_t = nu + (size_t)(t - g0) * plane;
+                e = dpk::launch_pushforward(mu, L.Spad, pol_t, K, S, pay, scale, nu_t, L.Spad,
+                                            grad_lam + (size_t)(t - 1) * K, stream);
+                if (e != hipSuccess) return hip_fail(e, "pushforward");
+                // mu_{t+1} = P_t^T nu_t
+                e = dpk::launch_contract(P + (size_t)(t - 1) * K * K, true, nu_t, L.Spad, mu,
+                                         L.Spad, K, S, stream);
+                if (e != hipSuccess) return hip_fail(e, "transport");
+            }
+            e = dpk::launch_gradP(nu, plane, L.Spad, Vseg + (size_t)(g0 + 1 - t_lo) * KS, KS, K,
+                                  S, g1 - g0 + 1, grad_P + (size_t)(g0 - 1) * K * K, stream);
+            if (e != hipSuccess) return hip_fail(e, "grad_P");
         }
     }
     if (grad_vterm) {

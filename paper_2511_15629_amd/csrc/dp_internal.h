@@ -120,9 +120,10 @@ hipError_t launch_pushforward(const float *mu, int ldm, const int16_t *pol, int 
                               Payoff pay, const double *scale, float *nu, int ldn,
                               float *grad_lam, hipStream_t stream);
 hipError_t launch_adjoint_scale(const float *seed, size_t n, double *scale, hipStream_t stream);
-hipError_t launch_adjoint_mix(const float *nu, int ldn, const float *V, int K, int S,
-                              const float *Pt, float *gP, float *mu, int ldm,
-                              hipStream_t stream);
+// grad_P of G consecutive stages: stage g of the group reads nu + g nu_stride ([K][ldn])
+// and V + g v_stride ([K][S]) and writes gP + g K K.
+hipError_t launch_gradP(const float *nu, size_t nu_stride, int ldn, const float *V,
+                        size_t v_stride, int K, int S, int G, float *gP, hipStream_t stream);
 hipError_t launch_copy_rows(const float *src, int lds, float *dst, int ldd, int K, int S,
                             hipStream_t stream);
 hipError_t launch_fill(float *dst, size_t n, float v, hipStream_t stream);

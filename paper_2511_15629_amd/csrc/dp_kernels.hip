@@ -1116,31 +1116,24 @@ hipError_t launch_adjoint_scale(const float *seed, size_t n, double *scale, hipS
 }
 
 // ------------------------------------------------------------------------------------
-// One launch for the two products that consume nu_t, 16 waves per block:
-//   blocks [0, nG):  grad_P_t = nu_t V_{t+1}^T, one 16 x 16 tile per block; wave w reduces
-//                    the w-th sixteenth of j (one chunk of prefetched MFMA steps), and the
-//                    16 partial tiles are added in wave order;
-//   blocks [nG, ..): mu_{t+1} = P_t^T nu_t, the expectation tile function with A = P^T,
-//                    one tile per wave.
+// grad_P_t = nu_t V_{t+1}^T for a group of consecutive stages (one launch per group; the
+// transport mu_{t+1} = P_t^T nu_t is the expectation kernel with A = P^T, per stage).
+// Block (x, y) = one 16 x 16 tile of stage y of the group, 16 waves: wave w reduces the
+// w-th sixteenth of j (one chunk of prefetched MFMA steps), and the 16 partial tiles are
+// added in wave order, so each gradient entry has one fixed summation order.
 // ------------------------------------------------------------------------------------
-constexpr int MIX_WAVES = 16;
+constexpr int GRADP_WAVES = 16;
 
-__global__ __launch_bounds__(64 * MIX_WAVES) void adjoint_mix_kernel(
-    const float *__restrict__ nu, int ldn, const float *__restrict__ V, int K, int S,
-    const float *__restrict__ Pt, float *__restrict__ gP, float *__restrict__ mu, int ldm, int nG)
+__global__ __launch_bounds__(64 * GRADP_WAVES) void gradP_kernel(
+    const float *__restrict__ nu0, size_t nu_stride, int ldn, const float *__restrict__ V0,
+    size_t v_stride, int K, int S, float *__restrict__ gP0)
 {
     constexpr int CH = 16;
-    __shared__ float part[MIX_WAVES][256];
+    __shared__ float part[GRADP_WAVES][256];
+    const float *nu = nu0 + blockIdx.y * nu_stride;
+    const float *V = V0 + blockIdx.y * v_stride;
+    float *gP = gP0 + (size_t)blockIdx.y * K * K;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    if ((int)blockIdx.x >= nG) {
-        const int ntm = (K + 15) >> 4, ntn = (S + 15) >> 4;
-        const int wid = (blockIdx.x - nG) * MIX_WAVES + wave;
-        if (wid >= ntm * ntn) return;
-        // chunks of 16 steps keep the 1024-thread block within its registers; the chunk
-        // size changes only when loads are issued, not the MFMA chain
-        contract_tile<true, 16>(Pt, nu, ldn, mu, ldm, K, S, wid % ntm, wid / ntm);
-        return;
-    }
     const int ntm = (K + 15) >> 4;
     const int tm = blockIdx.x % ntm, tn = blockIdx.x / ntm;
     const int kq = lane >> 4;
@@ -1148,7 +1141,7 @@ __global__ __launch_bounds__(64 * MIX_WAVES) void adjoint_mix_kernel(
     const int bcol = tn * 16 + (lane & 15);   // k'
     const bool rok = arow < K, cok = bcol < K;
     const int steps = (S + 3) / 4;
-    const int per = (steps + MIX_WAVES - 1) / MIX_WAVES;
+    const int per = (steps + GRADP_WAVES - 1) / GRADP_WAVES;
     const int jb = wave * per * 4, je = min(S, (wave + 1) * per * 4);
     floatx4 acc = {0.f, 0.f, 0.f, 0.f};
     for (int j0 = jb; j0 < je; j0 += 4 * CH) {
@@ -1172,20 +1165,17 @@ __global__ __launch_bounds__(64 * MIX_WAVES) void adjoint_mix_kernel(
         const int kr = tm * 16 + r, kc = tn * 16 + c;
         float sum = part[0][tid];
 #pragma unroll
-        for (int w = 1; w < MIX_WAVES; ++w) sum += part[w][tid];
+        for (int w = 1; w < GRADP_WAVES; ++w) sum += part[w][tid];
         if (kr < K && kc < K) gP[(size_t)kr * K + kc] = sum;
     }
 }
 
-hipError_t launch_adjoint_mix(const float *nu, int ldn, const float *V, int K, int S,
-                              const float *Pt, float *gP, float *mu, int ldm, hipStream_t stream)
+hipError_t launch_gradP(const float *nu, size_t nu_stride, int ldn, const float *V,
+                        size_t v_stride, int K, int S, int G, float *gP, hipStream_t stream)
 {
     const int nt = (K + 15) / 16;
-    const int nG = nt * nt;
-    const int tiles = nt * ((S + 15) / 16);
-    const int nB = (tiles + MIX_WAVES - 1) / MIX_WAVES;
-    hipLaunchKernelGGL(adjoint_mix_kernel, dim3(nG + nB), dim3(64 * MIX_WAVES), 0, stream, nu,
-                       ldn, V, K, S, Pt, gP, mu, ldm, nG);
+    hipLaunchKernelGGL(gradP_kernel, dim3(nt * nt, G), dim3(64 * GRADP_WAVES), 0, stream, nu,
+                       nu_stride, ldn, V, v_stride, K, S, gP);
     return hipGetLastError();
 }
 
