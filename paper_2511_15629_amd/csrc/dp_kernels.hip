@@ -1037,9 +1037,13 @@ hipError_t launch_init_terminal(const float *src, const double *src_off, int K, 
 // on the order the lanes reach LDS.  2^e is chosen from a bound B on sum |mu| (the adjoint
 // is mass-preserving under row-stochastic P, so B = 2 sum |seed| bounds every stage):
 // 2^e B <= 2^61 keeps every partial sum inside int64, and the rounding of each mass is at
-// most 2^-62 B.  grad_lam[k] = sum_s mu[s] g(pi(s) - s) uses per-lane sums and a
-// fixed-order tree.  One block per price state.
+// most 2^-62 B.  grad_lam[k] = sum_s mu[s] g(pi(s) - s) uses per-lane sums, a fixed
+// butterfly within each wave and the waves' sums in wave order.  One block per price
+// state; the block's policy and mass loads (up to PF per thread) and the scale are issued
+// before the accumulator is cleared, so the block waits for one memory round trip.
 // ------------------------------------------------------------------------------------
+constexpr int PF = 8;
+
 __global__ __launch_bounds__(1024) void pushforward_kernel(const float *__restrict__ mu,
                                                            int ldm,
                                                            const int16_t *__restrict__ pol,
@@ -1050,30 +1054,49 @@ __global__ __launch_bounds__(1024) void pushforward_kernel(const float *__restri
 {
     extern __shared__ float4 smem4[];
     unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem4);   // [S]
-    __shared__ float red[1024];
+    __shared__ float red[16];
     const int k = blockIdx.x;
     const int tid = threadIdx.x, nt = blockDim.x;
+    const int16_t *pk = pol + (size_t)k * S;
+    const float *mk = mu + (size_t)k * ldm;
+    int jv[PF];
+    float mv[PF];
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+        const int s = tid + u * nt;
+        jv[u] = s < S ? pk[s] : 0;
+        mv[u] = s < S ? mk[s] : 0.0f;
+    }
+    const double sc = scale[0];
     for (int i = tid; i < S; i += nt) acc[i] = 0ull;
     __syncthreads();
-    const double sc = scale[0];
     float gl = 0.0f;
-    for (int s = tid; s < S; s += nt) {
-        const int j = pol[(size_t)k * S + s];
-        const float m = mu[(size_t)k * ldm + s];
-        gl = fmaf(m, move_energy(j - s, pay), gl);
-        const long long q = llrint((double)m * sc);
-        atomicAdd(&acc[j], (unsigned long long)q);
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+        const int s = tid + u * nt;
+        if (s < S) {
+            gl = fmaf(mv[u], move_energy(jv[u] - s, pay), gl);
+            atomicAdd(&acc[jv[u]], (unsigned long long)llrint((double)mv[u] * sc));
+        }
     }
-    red[tid] = gl;
+    for (int s = tid + PF * nt; s < S; s += nt) {      // beyond the preloaded elements
+        const int j = pk[s];
+        const float m = mk[s];
+        gl = fmaf(m, move_energy(j - s, pay), gl);
+        atomicAdd(&acc[j], (unsigned long long)llrint((double)m * sc));
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) gl += __shfl_xor(gl, o);
+    if ((tid & 63) == 0) red[tid >> 6] = gl;
     __syncthreads();
     const double inv = 1.0 / sc;
     for (int i = tid; i < S; i += nt)
         nu[(size_t)k * ldn + i] = (float)((double)(long long)acc[i] * inv);
-    for (int w = nt >> 1; w > 0; w >>= 1) {
-        if (tid < w) red[tid] += red[tid + w];
-        __syncthreads();
+    if (tid == 0) {
+        float sum = red[0];
+        for (int w = 1; w < (nt >> 6); ++w) sum += red[w];
+        grad_lam[k] = sum;
     }
-    if (tid == 0) grad_lam[k] = red[0];
 }
 
 hipError_t launch_pushforward(const float *mu, int ldm, const int16_t *pol, int K, int S,
