@@ -1,11 +1,13 @@
-"""Properties of the GPU solve that hold at any size, checked at the full five-minute day
-shape (T = 288, K = 100, S = 1001, moves -250..250), where the oracle is too slow to
-re-derive every output.
+"""Properties of the GPU solves that hold at any size, checked at full sizes where the
+oracle is too slow to re-derive every output: the five-minute day (T = 288, K = 100,
+S = 1001, moves -250..250), a Table 3 shape of the paper mode (T = 8784, R = 200, S = 2001,
+P = 203) and the 512-battery fleet.
 
 * Homogeneity in the prices: with no throughput or start cost, the payoff of Eq. (1) and
   the recursion of Eq. (5)-(6) are positively homogeneous in (lam, V).  Doubling lam is
   exact in binary floating point (every product, sum, maximum and normalisation offset
-  doubles exactly), so the values double bit for bit and the policies are unchanged.
+  doubles exactly), so the values double bit for bit and the policies are unchanged.  The
+  same holds for the paper mode (payoff lam p, interpolated endpoints) and for the batch.
 * Relabelling the price states permutes the value rows (the expectation sums in another
   order, so within the FP32 tolerance).
 * A constant terminal value c adds c to every V_t, since every row of P_t sums to 1
@@ -82,3 +84,38 @@ def test_constant_terminal_value_shifts_every_stage(dp, day):
     print(f"terminal shift {c}: normwise value error {err:.2e}")
     assert err <= RTOL
     assert torch.equal(b["V"][-1], v_term)
+
+
+def test_paper_mode_doubling_prices_doubles_values_bitwise(dp):
+    # the Table 3 shape S = 2001, P = 203 (20 h, delta = 0.01), full year, R = 200
+    inst = wl.table3_instance(20, 0.01)
+    lam, prob = dev(inst.lam), dev(inst.prob)
+    kw = dict(store_all=True, policy=True)
+    a = dp.solve_independent(lam, prob, inst.S, inst.delta, inst.eta, inst.p_bar, **kw)
+    b = dp.solve_independent(2.0 * lam, prob, inst.S, inst.delta, inst.eta, inst.p_bar, **kw)
+    torch.cuda.synchronize()
+    assert torch.equal(b["V"], 2.0 * a["V"])
+    assert torch.equal(b["policy"], a["policy"])
+
+
+def test_fleet_doubling_prices_doubles_values_bitwise(dp):
+    insts = wl.fleet_5min()
+    sts = [dataclasses.replace(i.storage, c_deg=0.0, c_start=0.0) for i in insts]
+    plan = dp.BatchPlan([(i.T, i.K, st) for i, st in zip(insts, sts)])
+    Ps = {}
+    for i in insts:
+        if id(i.P) not in Ps:
+            Ps[id(i.P)] = dev(i.P)
+    P = [Ps[id(i.P)] for i in insts]
+    out = []
+    for scale in (1.0, 2.0):
+        lams = [dev(scale * i.lam) for i in insts]
+        V1 = [torch.empty(i.K, i.storage.S, device="cuda") for i in insts]
+        pol = [torch.empty(i.T, i.K, i.storage.S, dtype=torch.int16, device="cuda") for i in insts]
+        plan.solve(lams, P, V1, pol)
+        torch.cuda.synchronize()
+        out.append((V1, pol))
+    plan.close()
+    for n, inst in enumerate(insts):
+        assert torch.equal(out[1][0][n], 2.0 * out[0][0][n]), inst.name
+        assert torch.equal(out[1][1][n], out[0][1][n]), inst.name
