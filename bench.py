@@ -176,9 +176,18 @@ def cpu_baseline(inst, budget_s=12.0):
         if time.perf_counter() - t0 >= budget_s:
             break
     dt = time.perf_counter() - t0
+    # the same oracle on one thread, over the last 24 stages of the workload (a bounded
+    # sample; every stage has the same candidate count)
+    T1 = min(24, inst.T)
+    lam1, P1 = inst.lam[-T1:], inst.P[-T1:]
+    t1 = time.perf_counter()
+    oracle.solve(inst.storage, lam1, P1, keep_all=False, want_policy=True, threads=1)
+    dt1 = time.perf_counter() - t1
     return {"value": round(inst.candidates() * n / dt, 1), "unit": "updates/s", "cores": cores,
             "kind": "oracle",
-            "sample": f"{n} full solve(s) of {inst.name} (FP64 C loops, OpenMP over k)"}
+            "sample": f"{n} full solve(s) of {inst.name} (FP64 C loops, OpenMP over k)",
+            "single_thread": {"value": round(inst.candidates() / inst.T * T1 / dt1, 1),
+                              "sample": f"the last {T1} stages of {inst.name}, 1 thread"}}
 
 
 def adjoint_ratio(dp, torch, inst, reps=5):
