@@ -30,6 +30,8 @@ import time
 # one candidate needs at least one v_add_f32 and half a v_max3_f32 (1.5 instructions).
 VALU_LANE_OPS = 256 * 64 * 2.4e9
 SWEEP_PEAK_GUPD = VALU_LANE_OPS / 1.5 / 1e9
+# Dense FP32 matrix-core peak of the MI355X (published): 157.3 TFLOP/s.
+MFMA_F32_PEAK_TFLOPS = 157.3
 
 
 def host_cores() -> int:
@@ -154,13 +156,20 @@ def roofline_of(inst, timing, traffic=None):
     per_launch = inst.candidates() / inst.T            # candidates per sweep launch (avg)
     avg_s = sweep_ms / 1e3 / max(n_sweep, 1)
     achieved = per_launch / avg_s / 1e9
+    exp_avg = max(exp_ms / 1e3 / max(n_exp, 1), 1e-12)
+    exp_flop = 2.0 * inst.K * inst.K * inst.storage.S
     return {
         "bound": "alu", "achieved": round(achieved, 1), "peak": round(SWEEP_PEAK_GUPD, 1),
         "unit": "Gupd/s", "frac": round(achieved / SWEEP_PEAK_GUPD, 4), "traffic": traffic,
         "traffic_GBps": None if traffic is None else round(traffic / avg_s / 1e9, 1),
         "kernel": "sweep_kernel", "avg_launch_us": round(avg_s * 1e6, 3),
         "launches": n_sweep,
-        "expectation_avg_launch_us": round(exp_ms / 1e3 / max(n_exp, 1) * 1e6, 3),
+        "expectation_avg_launch_us": round(exp_avg * 1e6, 3),
+        # the expectation W_t = P_t V_{t+1} on the FP32 matrix cores: 2 K^2 S flop per launch
+        "expectation": {"bound": "mfma", "achieved": round(exp_flop / exp_avg / 1e12, 3),
+                        "peak": MFMA_F32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(exp_flop / exp_avg / 1e12 / MFMA_F32_PEAK_TFLOPS, 4),
+                        "kernel": "contract_kernel"},
     }
 
 
