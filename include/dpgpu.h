@@ -56,7 +56,7 @@ extern "C" {
 #define DP_EHIP     -4   /* a HIP runtime call failed                                    */
 #define DP_ETIMEOUT -5   /* reserved (no call of this version returns it)                 */
 #define DP_ENOMEM   -6   /* host allocation failed (plans only)                          */
-#define DP_ENOTSUP  -7   /* valid request outside what this build supports               */
+#define DP_ENOTSUP  -7   /* valid request outside what this library supports             */
 
 /* Limits. */
 #define DP_MAX_S 32767   /* next-state indices are stored as int16                       */
@@ -97,7 +97,7 @@ const char *dp_last_error(void);
  * R outputs per lane, D moves per chunk, NW waves per block, NSPLIT blocks of the move
  * range (NW % NSPLIT == 0).  R = 0 restores the built-in choice.  The shape never changes
  * results: every shape yields bitwise the same values and policies.  DP_EINVAL for a
- * shape this build has no kernel for; a later solve whose move window does not fit the
+ * shape this library has no kernel for; a later solve whose move window does not fit the
  * forced shape's LDS returns DP_ENOTSUP.  Not thread-safe with concurrent solves. */
 int dp_set_sweep_shape(int R, int D, int NW, int NSPLIT);
 

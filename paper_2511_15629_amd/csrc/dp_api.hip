@@ -242,7 +242,7 @@ const char *dp_strerror(int code)
     case DP_EHIP: return "HIP runtime error";
     case DP_ETIMEOUT: return "reserved error code";
     case DP_ENOMEM: return "host allocation failed";
-    case DP_ENOTSUP: return "not supported by this build";
+    case DP_ENOTSUP: return "not supported by this library";
     default: return "unknown error";
     }
 }
