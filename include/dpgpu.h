@@ -189,9 +189,9 @@ int dp_solve_iid(const dp_iid_problem *pb, const float *lam, const float *prob, 
 /* Batched solves of many independent instances (not in the paper; Sec. V's duration sweeps
  * are such batches).  All instances advance stage-synchronously: batch stage tau puts
  * instance i at its own stage T_i - tau + 1.  Instances are grouped by expectation kernel
- * (K <= 32, <= 64, <= 128, > 128); each group is one stream of launches (per tau, one
- * expectation launch, then one sweep launch per tile class that has instances in the
- * group), and the groups run concurrently.  A plan owns the device descriptor table,
+ * (K <= 32, <= 64, two alternating halves of K <= 128, and K > 128); each group is one
+ * stream of launches (per tau, one expectation launch, then one sweep launch per tile
+ * class that has instances in the group), and the groups run concurrently.  A plan owns the device descriptor table,
  * the work tables, its device workspace (one solver region per instance) and a HIP graph of
  * the whole launch sequence, captured once at creation; it is created for a fixed list of
  * problems (host array probs[n], flags must be 0, ckpt_every ignored) and replayed with new

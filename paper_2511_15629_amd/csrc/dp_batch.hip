@@ -34,18 +34,21 @@ const dpk::SweepShape kCandidates[] = {
     {4, 4, 1, 1},
 };
 
-// Instances fall into independent groups by expectation kernel: panel classes 0..2
-// (K <= 32, <= 64, <= 128) and strips (K > 128).  Each group is one branch of the graph.
-constexpr int NGROUPS = 4;
-
-int expectation_group(int K) { return K <= 128 ? dpk::panel_class(K) : 3; }
+// Instances fall into independent groups, one branch of the graph each.  Panel class c
+// (K <= 32, <= 64, <= 128) is dealt round-robin into SPLIT[c] groups, so that one group's
+// sweeps can run beside another's expectation; the last group holds the strips (K > 128).
+// Splitting the costliest class in two gives four panel branches, one per hardware queue
+// of a process; more branches than queues measured slower.
+constexpr int SPLIT[3] = {1, 1, 2};
+constexpr int STRIP_GROUP = SPLIT[0] + SPLIT[1] + SPLIT[2];
+constexpr int NGROUPS = STRIP_GROUP + 1;
 
 struct TileClass {
     dpk::SweepShape sh;
     int span_lo, span_hi;
     std::vector<int> inst;
     std::vector<dpk::SweepItem> items;      // ordered by group, then heavier instances first
-    int goff[NGROUPS] = {0, 0, 0, 0}, gn[NGROUPS] = {0, 0, 0, 0};
+    int goff[NGROUPS] = {}, gn[NGROUPS] = {};
     dpk::SweepItem *d_items = nullptr;
     size_t lds = 0;
     double tuned_us = -1.0;
@@ -77,6 +80,7 @@ struct dp_batch_plan {
     int n = 0;
     int Tmax = 0;
     std::vector<dp_problem> probs;
+    std::vector<int> group;                // branch of each instance
     std::vector<dpk::BatchDesc> hdesc;
     std::vector<size_t> region;            // per-instance workspace offsets
     dpk::BatchDesc *ddesc = nullptr;
@@ -85,8 +89,8 @@ struct dp_batch_plan {
     dpk::ContractItem *d_citems = nullptr;     // strip items (instances with K > 128)
     int n_citems = 0;
     dpk::ContractItem *d_pitems = nullptr;     // panel items (instances with K <= 128),
-    int n_pitems = 0;                          // grouped by dpk::panel_class
-    int pan_off[3] = {0, 0, 0}, pan_n[3] = {0, 0, 0}, pan_kmax[3] = {0, 0, 0};
+    int n_pitems = 0;                          // contiguous per group
+    int pan_off[NGROUPS] = {}, pan_n[NGROUPS] = {}, pan_kmax[NGROUPS] = {};
     char *ws = nullptr;
     size_t ws_bytes = 0;
     hipStream_t cap = nullptr;
@@ -128,12 +132,12 @@ static int enqueue_group(dp_batch_plan *p, int g, hipStream_t s)
 {
     hipError_t e = hipSuccess;
     for (int tau = 1; tau <= p->Tmax; ++tau) {
-        if (g < 3 && p->pan_n[g]) {
+        if (g != STRIP_GROUP && p->pan_n[g]) {
             e = dpk::launch_batched_panel(p->ddesc, p->d_pitems + p->pan_off[g], p->pan_n[g], tau,
                                           p->pan_kmax[g], s);
             if (e != hipSuccess) return hip_fail(e, "batched expectation (panels)");
         }
-        if (g == 3 && p->n_citems) {
+        if (g == STRIP_GROUP && p->n_citems) {
             e = dpk::launch_batched_contract(p->ddesc, p->d_citems, p->n_citems, tau, s);
             if (e != hipSuccess) return hip_fail(e, "batched expectation (strips)");
         }
@@ -149,7 +153,7 @@ static int enqueue_group(dp_batch_plan *p, int g, hipStream_t s)
 
 static bool group_used(const dp_batch_plan *p, int g)
 {
-    if (g < 3 ? p->pan_n[g] > 0 : p->n_citems > 0) return true;
+    if (g != STRIP_GROUP ? p->pan_n[g] > 0 : p->n_citems > 0) return true;
     for (auto &c : p->classes)
         if (c.gn[g]) return true;
     return false;
@@ -189,7 +193,7 @@ static int build_items(dp_batch_plan *p, TileClass &c)
     // spans, more outputs) first, for a short tail
     std::vector<int> order = c.inst;
     std::sort(order.begin(), order.end(), [&](int a, int b) {
-        const int ga = expectation_group(p->probs[a].K), gb = expectation_group(p->probs[b].K);
+        const int ga = p->group[a], gb = p->group[b];
         if (ga != gb) return ga < gb;
         const auto &x = p->probs[a].st, &y = p->probs[b].st;
         return (long)(x.w_up + x.w_down) * p->probs[a].K > (long)(y.w_up + y.w_down) * p->probs[b].K;
@@ -197,7 +201,7 @@ static int build_items(dp_batch_plan *p, TileClass &c)
     for (int g = 0; g < NGROUPS; ++g) c.gn[g] = 0;
     for (int i : order) {
         const dp_problem &pb = p->probs[i];
-        const int g = expectation_group(pb.K);
+        const int g = p->group[i];
         if (c.gn[g] == 0) c.goff[g] = (int)c.items.size();
         const int tiles = (pb.st.S + TS - 1) / TS;
         for (int k = 0; k < pb.K; ++k)
@@ -320,6 +324,19 @@ int dp_batch_plan_create(dp_batch_plan **out, int n, const dp_problem *probs,
     if (!p) return fail(DP_ENOMEM, "plan allocation");
     p->n = n;
     p->probs.assign(probs, probs + n);
+    p->group.resize(n);
+    int dealt[3] = {0, 0, 0};
+    for (int i = 0; i < n; ++i) {
+        const int K = probs[i].K;
+        if (K > 128) {
+            p->group[i] = STRIP_GROUP;
+            continue;
+        }
+        const int c = dpk::panel_class(K);
+        int g0 = 0;
+        for (int q = 0; q < c; ++q) g0 += SPLIT[q];
+        p->group[i] = g0 + (dealt[c]++) % SPLIT[c];
+    }
     size_t total = 0;
     for (int i = 0; i < n; ++i) {
         int rc = validate_problem(&p->probs[i]);
@@ -357,7 +374,7 @@ int dp_batch_plan_create(dp_batch_plan **out, int n, const dp_problem *probs,
     p->ws_bytes = total;
     const float *zeros_lam = reinterpret_cast<const float *>(p->ws + zoff);
     p->hdesc.resize(n);
-    std::vector<dpk::ContractItem> citems, pclass[3];
+    std::vector<dpk::ContractItem> citems, pgroup[NGROUPS];
     for (int i = 0; i < n; ++i) {
         const dp_problem &pb = p->probs[i];
         const SolveLayout L = solve_layout(&pb);
@@ -384,11 +401,11 @@ int dp_batch_plan_create(dp_batch_plan **out, int n, const dp_problem *probs,
         if (pb.K <= 128) {
             // items of up to four panels (P_t staged once per item); two for K > 64, whose
             // items are long enough that finer ones balance the CUs better
-            const int c = dpk::panel_class(pb.K);
+            const int c = dpk::panel_class(pb.K), g = p->group[i];
             const int ppi = c == 2 ? 2 : 4;
             for (int tn = 0; tn < ntn; tn += 4 * ppi)
-                pclass[c].push_back({i, std::min(ppi, (ntn - tn + 3) / 4), tn});
-            p->pan_kmax[c] = std::max(p->pan_kmax[c], pb.K);
+                pgroup[g].push_back({i, std::min(ppi, (ntn - tn + 3) / 4), tn});
+            p->pan_kmax[g] = std::max(p->pan_kmax[g], pb.K);
         } else {
             for (int tn = 0; tn < ntn; tn += 4)
                 for (int tm = 0; tm < ntm; ++tm) citems.push_back({i, tm, tn});
@@ -396,10 +413,10 @@ int dp_batch_plan_create(dp_batch_plan **out, int n, const dp_problem *probs,
     }
     p->n_citems = (int)citems.size();
     std::vector<dpk::ContractItem> pitems;
-    for (int c = 0; c < 3; ++c) {
-        p->pan_off[c] = (int)pitems.size();
-        p->pan_n[c] = (int)pclass[c].size();
-        pitems.insert(pitems.end(), pclass[c].begin(), pclass[c].end());
+    for (int g = 0; g < NGROUPS; ++g) {
+        p->pan_off[g] = (int)pitems.size();
+        p->pan_n[g] = (int)pgroup[g].size();
+        pitems.insert(pitems.end(), pgroup[g].begin(), pgroup[g].end());
     }
     p->n_pitems = (int)pitems.size();
     e = hipSuccess;
