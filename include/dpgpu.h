@@ -148,7 +148,10 @@ size_t dp_adjoint_workspace_bytes(const dp_problem *pb);
  * which case every segment of ckpt_every stages is recomputed from its checkpoint
  * (bitwise the same values and policies as the forward solve).
  *   seed [K][S]; outputs grad_lam [T][K], grad_P [T][K][K], grad_vterm [K][S] (or NULL).
- * Requires S <= 8192. */
+ * With ckpt, the re-solve of each segment runs on a library-owned stream of the current
+ * device (one per device, created on first use), overlapping the adjoint of the previous
+ * segment; it is forked from and joined back into `stream` with events, and calls from
+ * several threads are ordered on it.  Requires S <= 8192. */
 int dp_adjoint(const dp_problem *pb, const float *lam, const float *P, const float *v_term,
                const float *V_all, const int16_t *policy, const void *ckpt,
                const float *seed, float *grad_lam, float *grad_P, float *grad_vterm,

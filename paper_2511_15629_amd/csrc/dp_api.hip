@@ -7,6 +7,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -369,15 +370,63 @@ static AdjLayout adj_layout(const dp_problem *pb, bool ckpt_mode)
     L.nu = o; o += (size_t)L.G * plane;
     L.scale = o; o += 256;
     if (ckpt_mode) {
+        // two segment buffers: segment m + 1 is re-solved into one while the adjoint of
+        // segment m reads the other
         const int E = pb->ckpt_every > 0 ? pb->ckpt_every : 16;
         const size_t KS = (size_t)pb->K * pb->st.S;
-        L.vseg = o; o += align256(sizeof(float) * (size_t)(E + 1) * KS);
-        L.polseg = o; o += align256(sizeof(int16_t) * (size_t)E * KS);
+        L.vseg = o; o += 2 * align256(sizeof(float) * (size_t)(E + 1) * KS);
+        L.polseg = o; o += 2 * align256(sizeof(int16_t) * (size_t)E * KS);
         L.solve_ws = o; o += solve_layout(pb).total;
     }
     L.total = o;
     return L;
 }
+
+// A stream per device for the checkpointed adjoint's segment re-solves, created on first
+// use and kept until the process ends (default priority).  Calls that share it are ordered
+// on it; every use is forked from and joined back into the caller's stream with events.
+static hipError_t side_stream(hipStream_t *out)
+{
+    static std::mutex mu;
+    static std::vector<hipStream_t> streams;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(mu);
+    if ((int)streams.size() <= dev) streams.resize(dev + 1, nullptr);
+    if (!streams[dev]) {
+        e = hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            streams[dev] = nullptr;
+            return e;
+        }
+    }
+    *out = streams[dev];
+    return hipSuccess;
+}
+
+// Events of one checkpointed dp_adjoint call, destroyed on every return path (the runtime
+// releases an event destroyed before its recorded work completes once that work is done).
+struct AdjEvents {
+    hipEvent_t fork = nullptr, solved[2] = {nullptr, nullptr}, used[2] = {nullptr, nullptr};
+    ~AdjEvents()
+    {
+        if (fork) (void)hipEventDestroy(fork);
+        for (int i = 0; i < 2; ++i) {
+            if (solved[i]) (void)hipEventDestroy(solved[i]);
+            if (used[i]) (void)hipEventDestroy(used[i]);
+        }
+    }
+    hipError_t create()
+    {
+        hipError_t e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+        for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+            e = hipEventCreateWithFlags(&solved[i], hipEventDisableTiming);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&used[i], hipEventDisableTiming);
+        }
+        return e;
+    }
+};
 
 size_t dp_adjoint_workspace_bytes(const dp_problem *pb)
 {
@@ -419,56 +468,103 @@ int dp_adjoint(const dp_problem *pb, const float *lam, const float *P, const flo
     if (e != hipSuccess) return hip_fail(e, "adjoint scale");
 
     const int E = ckpt_mode ? pb->ckpt_every : T;
+    const int nseg = (T + E - 1) / E;
     float *cv = nullptr;
     double *co = nullptr;
     if (ckpt_mode) ckpt_pointers(pb, const_cast<void *>(ckpt), &cv, &co);
-    for (int t_lo = 1; t_lo <= T; t_lo += E) {
-        const int t_hi = t_lo + E - 1 < T ? t_lo + E - 1 : T;
-        const float *Vseg;       // slice (t - t_lo) holds V_t, slice t_hi + 1 - t_lo holds V_{t_hi+1}
-        const int16_t *pseg;
-        if (ckpt_mode) {
-            float *vs = reinterpret_cast<float *>(base + L.vseg);
-            int16_t *ps = reinterpret_cast<int16_t *>(base + L.polseg);
-            const float *src;
-            const double *src_off;
-            if (t_hi == T) {
-                src = v_term;
-                src_off = nullptr;
-            } else {
-                const int m = t_hi / E;          // stage t_hi + 1 = 1 + m E
-                src = cv + (size_t)(m - 1) * KS;
-                src_off = co + (m - 1);
-            }
-            StageOutputs out = {};
-            out.vall = vs;
-            out.pol = ps;
-            out.ckpt_every = E;
-            rc = run_stages(pb, t_lo, t_hi, lam, P, src, src_off, out, base + L.solve_ws, stream);
-            if (rc != DP_OK) return rc;
-            Vseg = vs;
-            pseg = ps;
-        } else {
-            Vseg = V_all + (size_t)(t_lo - 1) * KS;
-            pseg = policy + (size_t)(t_lo - 1) * KS;
-        }
-        for (int g0 = t_lo; g0 <= t_hi; g0 += L.G) {
-            const int g1 = g0 + L.G - 1 < t_hi ? g0 + L.G - 1 : t_hi;
-            for (int t = g0; t <= g1; ++t) {
-                const int16_t *pol_t = pseg + (size_t)(t - t_lo) * KS;
-                float *nu_t = nu + (size_t)(t - g0) * plane;
-                e = dpk::launch_pushforward(mu, L.Spad, pol_t, K, S, pay, scale, nu_t, L.Spad,
-                                            grad_lam + (size_t)(t - 1) * K, stream);
-                if (e != hipSuccess) return hip_fail(e, "pushforward");
-                // mu_{t+1} = P_t^T nu_t
-                e = dpk::launch_contract(P + (size_t)(t - 1) * K * K, true, nu_t, L.Spad, mu,
-                                         L.Spad, K, S, stream);
-                if (e != hipSuccess) return hip_fail(e, "transport");
-            }
-            e = dpk::launch_gradP(nu, plane, L.Spad, Vseg + (size_t)(g0 + 1 - t_lo) * KS, KS, K,
-                                  S, g1 - g0 + 1, grad_P + (size_t)(g0 - 1) * K * K, stream);
-            if (e != hipSuccess) return hip_fail(e, "grad_P");
-        }
+    const size_t vseg_bytes = align256(sizeof(float) * (size_t)(E + 1) * KS);
+    const size_t pseg_bytes = align256(sizeof(int16_t) * (size_t)E * KS);
+
+    // Checkpoint mode: segment m is re-solved backward from its checkpoint on a side stream
+    // into segment buffer m % 2, while this stream runs the adjoint of segment m - 1 from
+    // the other buffer.  solved[b] orders a re-solve before its adjoint; used[b] orders the
+    // adjoint of segment m before the re-solve of segment m + 2 rewrites its buffer.
+    hipStream_t side = nullptr;
+    AdjEvents ev;
+    hipEvent_t side_last = nullptr;     // the side stream's last recorded event (for the join)
+    if (ckpt_mode) {
+        e = side_stream(&side);
+        if (e == hipSuccess) e = ev.create();
+        if (e == hipSuccess) e = hipEventRecord(ev.fork, stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(side, ev.fork, 0);
+        if (e != hipSuccess) return hip_fail(e, "adjoint side stream");
     }
+    auto resolve = [&](int m) -> int {
+        const int t_lo = 1 + m * E, t_hi = t_lo + E - 1 < T ? t_lo + E - 1 : T;
+        const int b = m & 1;
+        if (m >= 2) {
+            const hipError_t ew = hipStreamWaitEvent(side, ev.used[b], 0);
+            if (ew != hipSuccess) return hip_fail(ew, "segment buffer wait");
+        }
+        const float *src;
+        const double *src_off;
+        if (t_hi == T) {
+            src = v_term;
+            src_off = nullptr;
+        } else {
+            const int mc = t_hi / E;         // stage t_hi + 1 = 1 + mc E
+            src = cv + (size_t)(mc - 1) * KS;
+            src_off = co + (mc - 1);
+        }
+        StageOutputs out = {};
+        out.vall = reinterpret_cast<float *>(base + L.vseg + b * vseg_bytes);
+        out.pol = reinterpret_cast<int16_t *>(base + L.polseg + b * pseg_bytes);
+        out.ckpt_every = E;
+        const int rs = run_stages(pb, t_lo, t_hi, lam, P, src, src_off, out, base + L.solve_ws, side);
+        if (rs != DP_OK) return rs;
+        const hipError_t er = hipEventRecord(ev.solved[b], side);
+        if (er != hipSuccess) return hip_fail(er, "segment event");
+        side_last = ev.solved[b];
+        return DP_OK;
+    };
+    auto stages = [&]() -> int {
+        if (ckpt_mode && (rc = resolve(0)) != DP_OK) return rc;
+        for (int m = 0; m < nseg; ++m) {
+            const int t_lo = 1 + m * E, t_hi = t_lo + E - 1 < T ? t_lo + E - 1 : T;
+            const float *Vseg;   // slice (t - t_lo) holds V_t, slice t_hi + 1 - t_lo holds V_{t_hi+1}
+            const int16_t *pseg;
+            if (ckpt_mode) {
+                if (m + 1 < nseg && (rc = resolve(m + 1)) != DP_OK) return rc;
+                e = hipStreamWaitEvent(stream, ev.solved[m & 1], 0);
+                if (e != hipSuccess) return hip_fail(e, "segment wait");
+                Vseg = reinterpret_cast<const float *>(base + L.vseg + (m & 1) * vseg_bytes);
+                pseg = reinterpret_cast<const int16_t *>(base + L.polseg + (m & 1) * pseg_bytes);
+            } else {
+                Vseg = V_all + (size_t)(t_lo - 1) * KS;
+                pseg = policy + (size_t)(t_lo - 1) * KS;
+            }
+            for (int g0 = t_lo; g0 <= t_hi; g0 += L.G) {
+                const int g1 = g0 + L.G - 1 < t_hi ? g0 + L.G - 1 : t_hi;
+                for (int t = g0; t <= g1; ++t) {
+                    const int16_t *pol_t = pseg + (size_t)(t - t_lo) * KS;
+                    float *nu_t = nu + (size_t)(t - g0) * plane;
+                    e = dpk::launch_pushforward(mu, L.Spad, pol_t, K, S, pay, scale, nu_t,
+                                                L.Spad, grad_lam + (size_t)(t - 1) * K, stream);
+                    if (e != hipSuccess) return hip_fail(e, "pushforward");
+                    // mu_{t+1} = P_t^T nu_t
+                    e = dpk::launch_contract(P + (size_t)(t - 1) * K * K, true, nu_t, L.Spad, mu,
+                                             L.Spad, K, S, stream);
+                    if (e != hipSuccess) return hip_fail(e, "transport");
+                }
+                e = dpk::launch_gradP(nu, plane, L.Spad, Vseg + (size_t)(g0 + 1 - t_lo) * KS,
+                                      KS, K, S, g1 - g0 + 1, grad_P + (size_t)(g0 - 1) * K * K,
+                                      stream);
+                if (e != hipSuccess) return hip_fail(e, "grad_P");
+            }
+            if (ckpt_mode) {
+                e = hipEventRecord(ev.used[m & 1], stream);
+                if (e != hipSuccess) return hip_fail(e, "segment event");
+            }
+        }
+        return DP_OK;
+    };
+    rc = stages();
+    if (side_last) {
+        // join: whatever the side stream was given is done before this call's later work
+        const hipError_t ej = hipStreamWaitEvent(stream, side_last, 0);
+        if (rc == DP_OK && ej != hipSuccess) rc = hip_fail(ej, "join");
+    }
+    if (rc != DP_OK) return rc;
     if (grad_vterm) {
         e = dpk::launch_copy_rows(mu, L.Spad, grad_vterm, S, K, S, stream);
         if (e != hipSuccess) return hip_fail(e, "grad_vterm copy");
