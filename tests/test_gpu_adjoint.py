@@ -101,6 +101,19 @@ def test_checkpointed_adjoint_is_bitwise_equal_to_full_storage(dp):
             assert torch.equal(g_full[key], g_ck[key]), (every, key)
 
 
+def test_checkpointed_adjoint_full_day_is_bitwise_equal(dp):
+    # 18 segments of 16 stages: the re-solves alternate between two segment buffers on a
+    # second stream while the adjoint of the previous segment runs; repeated twice so a
+    # later call reuses the library's stream and the segment buffers' contents
+    inst = wl.day_5min_adjoint()
+    om = wl.default_seed(inst.K, inst.storage.S)
+    _, g_full = gpu_forward_backward(dp, inst, om, 0)
+    for rep in range(2):
+        _, g_ck = gpu_forward_backward(dp, inst, om, 16)
+        for key in ("grad_lam", "grad_P", "grad_vterm"):
+            assert torch.equal(g_full[key], g_ck[key]), (rep, key)
+
+
 def test_adjoint_is_deterministic(dp):
     inst = wl.random_small(12, 12, 30, 700, 90, 60)
     om = np.random.default_rng(1).uniform(0, 1, size=(30, 700)).astype(np.float32)
