@@ -169,7 +169,7 @@ def roofline_of(inst, timing, traffic=None):
         "expectation": {"bound": "mfma", "achieved": round(exp_flop / exp_avg / 1e12, 3),
                         "peak": MFMA_F32_PEAK_TFLOPS, "unit": "TFLOP/s",
                         "frac": round(exp_flop / exp_avg / 1e12 / MFMA_F32_PEAK_TFLOPS, 4),
-                        "kernel": "contract_kernel"},
+                        "kernel": "contract_packed_kernel"},
     }
 
 

@@ -132,6 +132,12 @@ SolveLayout solve_layout(const dp_problem *pb)
     L.W = o; o += plane;
     L.off = o; o += align256(sizeof(double) * ((size_t)pb->T + 2));
     L.flag = o; o += 256;
+    // P_t repacked for the expectation, up to 32 stages per pack launch (<= 64 MB)
+    const size_t pk = sizeof(float) * dpk::packed_P_floats(pb->K);
+    L.npk = 32;
+    while (L.npk > 1 && (size_t)L.npk * pk > ((size_t)64 << 20)) L.npk >>= 1;
+    if (L.npk > pb->T) L.npk = pb->T;
+    L.Pp = o; o += align256((size_t)L.npk * pk);
     L.total = o;
     return L;
 }
@@ -187,12 +193,20 @@ int run_stages(const dp_problem *pb, int t_lo, int t_hi, const float *lam, const
     a.W = Wb;
     a.ldv = L.Spad;
     int cur = 0;
+    float *Pp = reinterpret_cast<float *>(base + L.Pp);
+    const size_t pk = dpk::packed_P_floats(K);
+    int pk_lo = t_hi + 1;          // the packed stages are pk_lo .. pk_lo + npk - 1
     for (int t = t_hi; t >= t_lo; --t) {
         const float *vin = vbuf[cur];
         float *vout = vbuf[cur ^ 1];
+        if (t < pk_lo) {           // repack the next chunk of stages (downwards from t)
+            pk_lo = t - L.npk + 1 > t_lo ? t - L.npk + 1 : t_lo;
+            e = dpk::launch_pack_P(P + (size_t)(pk_lo - 1) * K * K, K, t - pk_lo + 1, Pp, stream);
+            if (e != hipSuccess) return hip_fail(e, "pack P");
+        }
         if ((e = timer_mark(stream, 1, true)) != hipSuccess) return hip_fail(e, "timer");
-        e = dpk::launch_contract(P + (size_t)(t - 1) * K * K, false, vin, L.Spad, Wb, L.Spad, K,
-                                 S, stream);
+        e = dpk::launch_contract_packed(Pp + (size_t)(t - pk_lo) * pk, vin, L.Spad, Wb, L.Spad,
+                                        K, S, stream);
         if (e != hipSuccess) return hip_fail(e, "contract");
         if ((e = timer_mark(stream, 1, false)) != hipSuccess) return hip_fail(e, "timer");
         a.lam = lam + (size_t)(t - 1) * K;

@@ -12,7 +12,8 @@ dpk::SweepShape pick_shape(const dp_problem *pb);
 
 struct SolveLayout {
     int Spad;                 // row stride of the value planes and the W plane
-    size_t vA, vB, W, off, flag, total;
+    int npk;                  // stages of P_t held repacked for the expectation
+    size_t vA, vB, W, off, flag, Pp, total;
 };
 SolveLayout solve_layout(const dp_problem *pb);
 

@@ -153,6 +153,95 @@ __global__ __launch_bounds__(256) void contract_kernel(const float *__restrict__
     contract_tile<TRANS_A>(A, B, ldb, C, ldc, K, N, wid % ntm, wid / ntm);
 }
 
+// P_t in the lane order of the 16x16x4 instruction: for row tile tm and k-step st, the 64
+// A operands A[16 tm + i][4 st + kk] (lane i + 16 kk) are 64 consecutive floats, zero
+// outside the K x K matrix.  Each A load of the tile is then one coalesced 256-byte read
+// instead of 16 rows' 16-byte pieces.  Layout per stage: [ceil(K/16)][ceil(K/4)][64].
+size_t packed_P_floats(int K) { return (size_t)((K + 15) >> 4) * ((K + 3) >> 2) * 64; }
+
+__global__ void pack_P_kernel(const float *__restrict__ P, int K, int nstage,
+                              float *__restrict__ Pp)
+{
+    const int ntm = (K + 15) >> 4, nst = (K + 3) >> 2;
+    const size_t per = (size_t)ntm * nst * 64, n = per * nstage;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const size_t t = e / per, r = e - t * per;
+        const int l = (int)(r & 63), st = (int)((r >> 6) % nst), tm = (int)((r >> 6) / nst);
+        const int row = tm * 16 + (l & 15), col = 4 * st + (l >> 4);
+        Pp[e] = (row < K && col < K) ? P[t * K * K + (size_t)row * K + col] : 0.f;
+    }
+}
+
+hipError_t launch_pack_P(const float *P, int K, int nstage, float *Pp, hipStream_t stream)
+{
+    const size_t n = packed_P_floats(K) * nstage;
+    int blocks = (int)((n + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(pack_P_kernel, dim3(blocks), dim3(256), 0, stream, P, K, nstage, Pp);
+    return hipGetLastError();
+}
+
+// contract_tile with A = P_t read from the packed layout: the same operands in the same
+// MFMA order, so the results are bitwise those of contract_tile<false>.
+template <int CH = 32>
+__device__ __forceinline__ void contract_tile_packed(const float *__restrict__ Ap,
+                                                     const float *__restrict__ B, int ldb,
+                                                     float *__restrict__ C, int ldc, int K,
+                                                     int N, int tm, int tn)
+{
+    const int lane = threadIdx.x & 63;
+    const int kq = lane >> 4;
+    const int col = tn * 16 + (lane & 15);
+    const bool cok = col < N;
+    const int nst = (K + 3) >> 2;
+    const float *ap = Ap + (size_t)tm * nst * 64 + lane;
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 4 * CH) {
+        float av[CH], bv[CH];
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+            const int st = (k0 >> 2) + i;
+            const int kx = 4 * st + kq;
+            av[i] = st < nst ? ap[(size_t)st * 64] : 0.f;
+            bv[i] = (kx < K && cok) ? B[(size_t)kx * ldb + col] : 0.f;
+        }
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+            if (k0 + 4 * i < K) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[i], acc, 0, 0, 0);
+        }
+    }
+    if (cok) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = tm * 16 + 4 * kq + v;
+            if (r < K) C[(size_t)r * ldc + col] = acc[v];
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void contract_packed_kernel(const float *__restrict__ Ap,
+                                                              const float *__restrict__ B,
+                                                              int ldb, float *__restrict__ C,
+                                                              int ldc, int K, int N)
+{
+    const int ntm = (K + 15) >> 4;
+    const int ntn = (N + 15) >> 4;
+    const int wid = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wid >= ntm * ntn) return;
+    contract_tile_packed(Ap, B, ldb, C, ldc, K, N, wid % ntm, wid / ntm);
+}
+
+hipError_t launch_contract_packed(const float *Ap, const float *B, int ldb, float *C, int ldc,
+                                  int K, int N, hipStream_t stream)
+{
+    const int tiles = ((K + 15) / 16) * ((N + 15) / 16);
+    const int blocks = (tiles + 3) / 4;
+    hipLaunchKernelGGL(contract_packed_kernel, dim3(blocks), dim3(256), 0, stream, Ap, B, ldb,
+                       C, ldc, K, N);
+    return hipGetLastError();
+}
+
 hipError_t launch_contract(const float *A, bool transA, const float *B, int ldb, float *C,
                            int ldc, int K, int N, hipStream_t stream)
 {
