@@ -184,9 +184,9 @@ def test_fleet_of_512_batched_equals_looped(dp):
     torch.cuda.synchronize()
     for n in range(len(insts)):
         assert torch.equal(Vb[n], Vl[n]), insts[n].name
-    # oracle parity of V_1 on the three smallest instances
-    order = sorted(range(len(insts)), key=lambda n: insts[n].candidates())[:3]
-    for n in order:
+    # oracle parity of V_1 on the three smallest and the two largest instances
+    by_size = sorted(range(len(insts)), key=lambda n: insts[n].candidates())
+    for n in by_size[:3] + by_size[-2:]:
         inst = insts[n]
         ref = oracle.solve(inst.storage, inst.lam, inst.P, keep_all=False, want_policy=False)
         v = Vb[n].cpu().numpy().astype(np.float64)
