@@ -201,7 +201,8 @@ int run_stages(const dp_problem *pb, int t_lo, int t_hi, const float *lam, const
         float *vout = vbuf[cur ^ 1];
         if (t < pk_lo) {           // repack the next chunk of stages (downwards from t)
             pk_lo = t - L.npk + 1 > t_lo ? t - L.npk + 1 : t_lo;
-            e = dpk::launch_pack_P(P + (size_t)(pk_lo - 1) * K * K, K, t - pk_lo + 1, Pp, stream);
+            e = dpk::launch_pack_P(P + (size_t)(pk_lo - 1) * K * K, false, K, t - pk_lo + 1, Pp,
+                                   stream);
             if (e != hipSuccess) return hip_fail(e, "pack P");
         }
         if ((e = timer_mark(stream, 1, true)) != hipSuccess) return hip_fail(e, "timer");
@@ -366,7 +367,8 @@ int dp_solve(const dp_problem *pb, const float *lam, const float *P, const float
 // ------------------------------------------------------------------------------------
 struct AdjLayout {
     int Spad, G;            // G: stages per grad_P launch (nu_t planes kept for a group)
-    size_t mu, nu, scale, vseg, polseg, solve_ws, total;
+    int npk;                // stages of P_t^T held repacked for the transport
+    size_t mu, nu, scale, PpT, vseg, polseg, solve_ws, total;
 };
 
 static AdjLayout adj_layout(const dp_problem *pb, bool ckpt_mode)
@@ -383,6 +385,12 @@ static AdjLayout adj_layout(const dp_problem *pb, bool ckpt_mode)
     L.mu = o; o += plane;
     L.nu = o; o += (size_t)L.G * plane;
     L.scale = o; o += 256;
+    // P_t^T repacked for the transport, up to 32 stages per pack launch (<= 64 MB)
+    const size_t pk = sizeof(float) * dpk::packed_P_floats(pb->K);
+    L.npk = 32;
+    while (L.npk > 1 && (size_t)L.npk * pk > ((size_t)64 << 20)) L.npk >>= 1;
+    if (L.npk > pb->T) L.npk = pb->T;
+    L.PpT = o; o += align256((size_t)L.npk * pk);
     if (ckpt_mode) {
         // two segment buffers: segment m + 1 is re-solved into one while the adjoint of
         // segment m reads the other
@@ -531,6 +539,9 @@ int dp_adjoint(const dp_problem *pb, const float *lam, const float *P, const flo
         side_last = ev.solved[b];
         return DP_OK;
     };
+    float *PpT = reinterpret_cast<float *>(base + L.PpT);
+    const size_t pk = dpk::packed_P_floats(K);
+    int pk_lo = 1, pk_hi = 0;      // the packed stages are pk_lo .. pk_hi
     auto stages = [&]() -> int {
         if (ckpt_mode && (rc = resolve(0)) != DP_OK) return rc;
         for (int m = 0; m < nseg; ++m) {
@@ -555,9 +566,16 @@ int dp_adjoint(const dp_problem *pb, const float *lam, const float *P, const flo
                     e = dpk::launch_pushforward(mu, L.Spad, pol_t, K, S, pay, scale, nu_t,
                                                 L.Spad, grad_lam + (size_t)(t - 1) * K, stream);
                     if (e != hipSuccess) return hip_fail(e, "pushforward");
-                    // mu_{t+1} = P_t^T nu_t
-                    e = dpk::launch_contract(P + (size_t)(t - 1) * K * K, true, nu_t, L.Spad, mu,
-                                             L.Spad, K, S, stream);
+                    // mu_{t+1} = P_t^T nu_t, A = P_t^T from the repacked ring
+                    if (t > pk_hi) {       // repack the next chunk of stages (upwards from t)
+                        pk_lo = t;
+                        pk_hi = t + L.npk - 1 < T ? t + L.npk - 1 : T;
+                        e = dpk::launch_pack_P(P + (size_t)(t - 1) * K * K, true, K,
+                                               pk_hi - pk_lo + 1, PpT, stream);
+                        if (e != hipSuccess) return hip_fail(e, "pack P^T");
+                    }
+                    e = dpk::launch_contract_packed(PpT + (size_t)(t - pk_lo) * pk, nu_t, L.Spad,
+                                                    mu, L.Spad, K, S, stream);
                     if (e != hipSuccess) return hip_fail(e, "transport");
                 }
                 e = dpk::launch_gradP(nu, plane, L.Spad, Vseg + (size_t)(g0 + 1 - t_lo) * KS,

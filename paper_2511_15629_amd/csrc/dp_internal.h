@@ -104,11 +104,12 @@ hipError_t launch_iid_init(float *V, int S, double *off, float *vabs, hipStream_
 // Stage kernels (launchers; all asynchronous on `stream`).
 hipError_t launch_contract(const float *A, bool transA, const float *B, int ldb, float *C,
                            int ldc, int K, int N, hipStream_t stream);
-// P_t of nstage consecutive stages repacked into the MFMA lane order (packed_P_floats(K)
-// floats per stage), and the expectation reading it; bitwise the same as launch_contract
-// with transA = false.
+// P_t (or P_t^T with transA) of nstage consecutive stages repacked into the MFMA lane
+// order (packed_P_floats(K) floats per stage), and the contraction reading it; bitwise the
+// same as launch_contract with the same transA.
 size_t packed_P_floats(int K);
-hipError_t launch_pack_P(const float *P, int K, int nstage, float *Pp, hipStream_t stream);
+hipError_t launch_pack_P(const float *P, bool transA, int K, int nstage, float *Pp,
+                         hipStream_t stream);
 hipError_t launch_contract_packed(const float *Ap, const float *B, int ldb, float *C, int ldc,
                                   int K, int N, hipStream_t stream);
 hipError_t launch_sweep(const SweepArgs &a, const SweepShape &sh, hipStream_t stream);

@@ -159,6 +159,8 @@ __global__ __launch_bounds__(256) void contract_kernel(const float *__restrict__
 // instead of 16 rows' 16-byte pieces.  Layout per stage: [ceil(K/16)][ceil(K/4)][64].
 size_t packed_P_floats(int K) { return (size_t)((K + 15) >> 4) * ((K + 3) >> 2) * 64; }
 
+// TRANS: pack P_t^T instead (A[r][c] = P_t[c][r]), for the adjoint's transport.
+template <bool TRANS>
 __global__ void pack_P_kernel(const float *__restrict__ P, int K, int nstage,
                               float *__restrict__ Pp)
 {
@@ -169,21 +171,27 @@ __global__ void pack_P_kernel(const float *__restrict__ P, int K, int nstage,
         const size_t t = e / per, r = e - t * per;
         const int l = (int)(r & 63), st = (int)((r >> 6) % nst), tm = (int)((r >> 6) / nst);
         const int row = tm * 16 + (l & 15), col = 4 * st + (l >> 4);
-        Pp[e] = (row < K && col < K) ? P[t * K * K + (size_t)row * K + col] : 0.f;
+        const size_t src = TRANS ? (size_t)col * K + row : (size_t)row * K + col;
+        Pp[e] = (row < K && col < K) ? P[t * K * K + src] : 0.f;
     }
 }
 
-hipError_t launch_pack_P(const float *P, int K, int nstage, float *Pp, hipStream_t stream)
+hipError_t launch_pack_P(const float *P, bool transA, int K, int nstage, float *Pp,
+                         hipStream_t stream)
 {
     const size_t n = packed_P_floats(K) * nstage;
     int blocks = (int)((n + 255) / 256);
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(pack_P_kernel, dim3(blocks), dim3(256), 0, stream, P, K, nstage, Pp);
+    if (transA)
+        hipLaunchKernelGGL(pack_P_kernel<true>, dim3(blocks), dim3(256), 0, stream, P, K, nstage, Pp);
+    else
+        hipLaunchKernelGGL(pack_P_kernel<false>, dim3(blocks), dim3(256), 0, stream, P, K, nstage, Pp);
     return hipGetLastError();
 }
 
-// contract_tile with A = P_t read from the packed layout: the same operands in the same
-// MFMA order, so the results are bitwise those of contract_tile<false>.
+// contract_tile with A read from the packed layout: the same operands in the same MFMA
+// order, so the results are bitwise those of contract_tile (A = P_t, or P_t^T when packed
+// transposed).
 template <int CH = 32>
 __device__ __forceinline__ void contract_tile_packed(const float *__restrict__ Ap,
                                                      const float *__restrict__ B, int ldb,
