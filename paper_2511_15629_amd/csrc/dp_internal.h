@@ -102,11 +102,9 @@ hipError_t launch_iid_tables(int S, double delta, double eta, double p_bar, IidE
 hipError_t launch_iid_init(float *V, int S, double *off, float *vabs, hipStream_t stream);
 
 // Stage kernels (launchers; all asynchronous on `stream`).
-hipError_t launch_contract(const float *A, bool transA, const float *B, int ldb, float *C,
-                           int ldc, int K, int N, hipStream_t stream);
 // P_t (or P_t^T with transA) of nstage consecutive stages repacked into the MFMA lane
 // order (packed_P_floats(K) floats per stage), and the contraction reading it; bitwise the
-// same as launch_contract with the same transA.
+// same as every other expectation kernel (the tile chain).
 size_t packed_P_floats(int K);
 hipError_t launch_pack_P(const float *P, bool transA, int K, int nstage, float *Pp,
                          hipStream_t stream);

@@ -40,54 +40,19 @@ __device__ __forceinline__ float move_reward(float lam, int d, const Payoff &p)
 // ------------------------------------------------------------------------------------
 // Expectation C = A * B on MFMA (v_mfma_f32_16x16x4_f32, FP32 products and accumulation).
 // A is K x K (P_t, or its transpose), B is K x N with leading dimension ldb, C is K x N.
-// One wave computes one 16 x 16 tile of C; the reduction over K runs in chunks of
-// CH MFMA steps (4 CH terms) whose operands are all loaded before the chunk's MFMA
-// chain starts, so a chunk costs one memory round trip, not one per step.  A single
-// solve has few tiles per stage and is latency-bound (CH = 32: one round trip up to
-// K = 128); a batch has tens of thousands of tiles in flight (CH = 8: fewer registers,
-// no wasted predicated loads for small K).
+// The tile chain: a 16 x 16 tile (tm, tn) of C is accumulated from zero over the k-steps
+// st = 0 .. ceil(K/4) - 1 in ascending order, one MFMA per step on A[16 tm + i][4 st + kk]
+// and B[4 st + kk][16 tn + j] (zero outside the matrices).  Every expectation kernel (the
+// single solve, the adjoint's transport, the batch's panels and strips) runs exactly this
+// chain per tile, so their results are bitwise equal.  The operand loads of a chunk of CH
+// steps are all issued before its MFMAs, so a chunk costs one memory round trip.
 // Lane layout of the 16x16x4 instruction: A[i][kk] from lane i + 16 kk, B[kk][j] from
 // lane j + 16 kk, result row 4 (lane / 16) + v, column lane % 16 in register v.
 // ------------------------------------------------------------------------------------
-template <bool TRANS_A, int CH = 32>
-__device__ __forceinline__ void contract_tile(const float *__restrict__ A,
-                                              const float *__restrict__ B, int ldb,
-                                              float *__restrict__ C, int ldc, int K, int N,
-                                              int tm, int tn)
-{
-    const int lane = threadIdx.x & 63;
-    const int arow = tm * 16 + (lane & 15);
-    const int kq = lane >> 4;
-    const int col = tn * 16 + (lane & 15);
-    const bool rok = arow < K, cok = col < N;
-    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < K; k0 += 4 * CH) {
-        float av[CH], bv[CH];
-#pragma unroll
-        for (int i = 0; i < CH; ++i) {
-            const int kx = k0 + 4 * i + kq;
-            const bool kok = kx < K;
-            av[i] = (kok && rok) ? (TRANS_A ? A[(size_t)kx * K + arow] : A[(size_t)arow * K + kx]) : 0.f;
-            bv[i] = (kok && cok) ? B[(size_t)kx * ldb + col] : 0.f;
-        }
-#pragma unroll
-        for (int i = 0; i < CH; ++i) {
-            if (k0 + 4 * i < K) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[i], acc, 0, 0, 0);
-        }
-    }
-    if (cok) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int r = tm * 16 + 4 * kq + v;
-            if (r < K) C[(size_t)r * ldc + col] = acc[v];
-        }
-    }
-}
-
 // Strip of NT adjacent 16 x 16 tiles (16 rows x 16 NT columns) per wave: each step loads
 // one A operand and NT B operands and issues NT MFMAs, so A loads and per-wave setup are
-// shared by NT tiles.  Each tile's MFMA chain (operands, order) is exactly that of
-// contract_tile, so the results are bitwise the same.
+// shared by NT tiles.  Each tile runs the tile chain (operands, order), so the results
+// are bitwise those of the other expectation kernels.
 template <int CH, int NT>
 __device__ __forceinline__ void contract_strip(const float *__restrict__ A,
                                                const float *__restrict__ B, int ldb,
@@ -140,19 +105,6 @@ __device__ __forceinline__ void contract_strip(const float *__restrict__ A,
     }
 }
 
-template <bool TRANS_A>
-__global__ __launch_bounds__(256) void contract_kernel(const float *__restrict__ A,
-                                                       const float *__restrict__ B, int ldb,
-                                                       float *__restrict__ C, int ldc, int K,
-                                                       int N)
-{
-    const int ntm = (K + 15) >> 4;
-    const int ntn = (N + 15) >> 4;
-    const int wid = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (wid >= ntm * ntn) return;
-    contract_tile<TRANS_A>(A, B, ldb, C, ldc, K, N, wid % ntm, wid / ntm);
-}
-
 // P_t in the lane order of the 16x16x4 instruction: for row tile tm and k-step st, the 64
 // A operands A[16 tm + i][4 st + kk] (lane i + 16 kk) are 64 consecutive floats, zero
 // outside the K x K matrix.  Each A load of the tile is then one coalesced 256-byte read
@@ -189,9 +141,8 @@ hipError_t launch_pack_P(const float *P, bool transA, int K, int nstage, float *
     return hipGetLastError();
 }
 
-// contract_tile with A read from the packed layout: the same operands in the same MFMA
-// order, so the results are bitwise those of contract_tile (A = P_t, or P_t^T when packed
-// transposed).
+// The tile chain with A read from the packed layout (A = P_t, or P_t^T when packed
+// transposed); CH = 32 loads every operand of a tile up to K = 128 in one round trip.
 template <int CH = 32>
 __device__ __forceinline__ void contract_tile_packed(const float *__restrict__ Ap,
                                                      const float *__restrict__ B, int ldb,
@@ -250,19 +201,6 @@ hipError_t launch_contract_packed(const float *Ap, const float *B, int ldb, floa
     return hipGetLastError();
 }
 
-hipError_t launch_contract(const float *A, bool transA, const float *B, int ldb, float *C,
-                           int ldc, int K, int N, hipStream_t stream)
-{
-    const int tiles = ((K + 15) / 16) * ((N + 15) / 16);
-    const int blocks = (tiles + 3) / 4;
-    if (transA)
-        hipLaunchKernelGGL(contract_kernel<true>, dim3(blocks), dim3(256), 0, stream, A, B, ldb, C,
-                           ldc, K, N);
-    else
-        hipLaunchKernelGGL(contract_kernel<false>, dim3(blocks), dim3(256), 0, stream, A, B, ldb,
-                           C, ldc, K, N);
-    return hipGetLastError();
-}
 
 // ------------------------------------------------------------------------------------
 // Max-plus Bellman sweep with argmax (Algorithm 1: gather, -inf mask, payoff, max).
@@ -877,7 +815,7 @@ __global__ __launch_bounds__(256) void batched_contract_kernel(const BatchDesc *
 // The tile loop is instantiated per k-step count NK = ceil(K/4):
 // all NK A operands of a tile are read from LDS ahead of a straight-line chain of NK MFMAs.
 // Rows beyond K read row K-1 (their outputs are discarded).  Every tile's chain is exactly
-// contract_tile's (NK MFMAs in k order on the same operands), so the results are bitwise
+// the tile chain (NK MFMAs in k order on the same operands), so the results are bitwise
 // the same.
 constexpr int PANEL_KMAX = 128;
 
