@@ -35,6 +35,7 @@ def small_batch():
         (4, 4, 5, 129, 128, 128, {}), (5, 6, 1, 10, 2, 3, {}), (6, 12, 8, 257, 3, 1, {}),
         (7, 6, 33, 600, 250, 250, dict(lam_lo=-150.0)), (8, 5, 12, 1001, 14, 18, dict(eta=0.86)),
         (9, 6, 2, 2, 1, 1, {}), (10, 7, 64, 512, 0, 0, {}),
+        (11, 1, 9, 150, 12, 9, {}), (12, 2, 40, 90, 30, 30, dict(c_start=1.0)),   # T = 1, 2 beside T = 12
     ]
     return [wl.random_small(sd, T, K, S, wu, wd, **kw) for (sd, T, K, S, wu, wd, kw) in specs]
 

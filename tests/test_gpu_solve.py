@@ -53,6 +53,8 @@ RAGGED = [
     dict(seed=7, T=5, K=64, S=512, wu=64, wd=64, c_deg=0.0),
     dict(seed=8, T=4, K=20, S=2001, wu=160, wd=190, eta=0.86),
     dict(seed=9, T=7, K=2, S=129, wu=1, wd=100),
+    dict(seed=10, T=1, K=6, S=300, wu=20, wd=35, c_start=1.0),    # a single stage
+    dict(seed=11, T=1, K=1, S=2, wu=1, wd=1),                     # the smallest problem
 ]
 
 
