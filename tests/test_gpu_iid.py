@@ -55,6 +55,8 @@ CASES = [
     dict(T=5, R=3, S=7, delta=0.5, eta=0.8, p_bar=2.0),        # power range beyond the storage
     dict(T=4, R=64, S=401, delta=0.01, eta=math.sqrt(0.85), p_bar=1.0),   # P = 203
     dict(T=7, R=2, S=33, delta=0.25, eta=1.0, p_bar=1.0),      # integral endpoints (b = 0)
+    dict(T=1, R=1, S=2, delta=0.5, eta=0.9, p_bar=0.3),        # one stage, one sample, two levels
+    dict(T=3, R=300, S=9, delta=0.2, eta=0.95, p_bar=0.1),     # power below one grid step
 ]
 
 
