@@ -64,6 +64,7 @@ CASES = [
     dict(seed=2, T=10, K=17, S=300, wu=30, wd=45),
     dict(seed=3, T=5, K=20, S=1001, wu=250, wd=250, lam_lo=-150.0),
     dict(seed=4, T=4, K=1, S=9, wu=2, wd=3),
+    dict(seed=5, T=1, K=4, S=30, wu=3, wd=4, c_start=0.5),    # a single stage
 ]
 
 
