@@ -200,7 +200,8 @@ int dp_solve_iid(const dp_iid_problem *pb, const float *lam, const float *prob, 
  * problems (host array probs[n], flags must be 0, ckpt_every ignored) and replayed with new
  * data.  tune_cache: path of a text cache of autotuned sweep tile shapes (created or
  * extended; the fastest shape per move-span class, timed at creation), or NULL to use the
- * built-in shapes without tuning.  Errors: DP_EINVAL (bad problem or pointer), DP_ENOMEM,
+ * built-in shapes without tuning (one- and two-wave tiles for move spans up to 256, four
+ * waves up to 512, the single solve's choice beyond).  Errors: DP_EINVAL (bad problem or pointer), DP_ENOMEM,
  * DP_EHIP.  The plan must be destroyed with dp_batch_plan_destroy. */
 typedef struct dp_batch_plan dp_batch_plan;
 

@@ -184,6 +184,18 @@ static int enqueue_all(dp_batch_plan *p, hipStream_t s)
     return DP_OK;
 }
 
+// Built-in sweep shape of a span class when no tuning is asked for: the shapes the tuner
+// picks for the five-minute fleet (one- and two-wave tiles of 256 and 512 outputs for short
+// rows, where a 1024-output tile leaves lanes idle on row tails), else the single solve's.
+static dpk::SweepShape batch_default_shape(const dp_problem *pb, int span_hi)
+{
+    dpk::SweepShape sh = span_hi <= 64    ? dpk::SweepShape{4, 8, 1, 1}
+                         : span_hi <= 256 ? dpk::SweepShape{4, 8, 2, 1}
+                         : span_hi <= 512 ? dpk::SweepShape{4, 16, 4, 1}
+                                          : pick_shape(pb);
+    return sh;
+}
+
 static int build_items(dp_batch_plan *p, TileClass &c)
 {
     c.items.clear();
@@ -448,7 +460,7 @@ int dp_batch_plan_create(dp_batch_plan **out, int n, const dp_problem *probs,
         c.inst = kv.second;
         c.span_lo = kv.first == 0 ? 1 : (16 << kv.first) + 1;
         c.span_hi = 32 << kv.first;
-        c.sh = pick_shape(&p->probs[c.inst[0]]);
+        c.sh = batch_default_shape(&p->probs[c.inst[0]], c.span_hi);
         auto it = cached.find(kv.first);
         bool fits_all = true;
         if (it != cached.end()) {
