@@ -267,9 +267,11 @@ static int autotune_class(dp_batch_plan *p, TileClass &c, const float *zeros_lam
         if ((rc = build_items(p, trial)) != DP_OK) break;
         // tau = 1 keeps every instance active (stage T_i); the W buffer holds zeros
         double t_min = 1e30;
-        for (int rep = 0; rep < 4 && rc == DP_OK; ++rep) {
+        // the minimum over 5 timed repeats of 6 stages (after one warm-up): single launches
+        // of the smaller classes last tens of microseconds, where one repeat is noisy
+        for (int rep = 0; rep < 6 && rc == DP_OK; ++rep) {
             e = hipEventRecord(e0, p->cap);
-            for (int st = 0; st < 3 && e == hipSuccess; ++st)
+            for (int st = 0; st < 6 && e == hipSuccess; ++st)
                 e = dpk::launch_batched_sweep(p->ddesc, trial.d_items, (int)trial.items.size(), 1,
                                               trial.sh, trial.lds, p->cap);
             if (e == hipSuccess) e = hipEventRecord(e1, p->cap);
@@ -277,7 +279,7 @@ static int autotune_class(dp_batch_plan *p, TileClass &c, const float *zeros_lam
             float ms = 0.f;
             if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
             if (e != hipSuccess) rc = hip_fail(e, "tune timing");
-            if (rep > 0) t_min = std::min(t_min, ms * 1e3 / 3.0);
+            if (rep > 0) t_min = std::min(t_min, ms * 1e3 / 6.0);
         }
         if (trial.d_items) (void)hipFree(trial.d_items);
         if (rc != DP_OK) break;
