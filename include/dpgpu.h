@@ -194,15 +194,18 @@ int dp_solve_iid(const dp_iid_problem *pb, const float *lam, const float *prob, 
  * instance i at its own stage T_i - tau + 1.  Instances are grouped by expectation kernel
  * (K <= 32, <= 64, two alternating halves of K <= 128, and K > 128); each group is one
  * stream of launches (per tau, one expectation launch, then one sweep launch per tile
- * class that has instances in the group), and the groups run concurrently.  A plan owns the device descriptor table,
- * the work tables, its device workspace (one solver region per instance) and a HIP graph of
- * the whole launch sequence, captured once at creation; it is created for a fixed list of
- * problems (host array probs[n], flags must be 0, ckpt_every ignored) and replayed with new
- * data.  tune_cache: path of a text cache of autotuned sweep tile shapes (created or
- * extended; the fastest shape per move-span class, timed at creation), or NULL to use the
- * built-in shapes without tuning (one- and two-wave tiles for move spans up to 256, four
- * waves up to 512, the single solve's choice beyond).  Errors: DP_EINVAL (bad problem or pointer), DP_ENOMEM,
- * DP_EHIP.  The plan must be destroyed with dp_batch_plan_destroy. */
+ * class that has instances in the group), and the groups run concurrently.
+ * A plan owns the device descriptor table, the work tables, its device workspace (one
+ * solver region per instance) and a HIP graph of the whole launch sequence, captured once
+ * at creation; it is created for a fixed list of problems (host array probs[n], flags must
+ * be 0, ckpt_every ignored) and replayed with new data.
+ * tune_cache: path of a text cache of autotuned sweep tile shapes (created or extended;
+ * the fastest shape per move-span class, timed at creation), or NULL to use the built-in
+ * shapes without tuning (one- and two-wave tiles for move spans up to 256, four waves up
+ * to 512, the single solve's choice beyond).
+ * Errors: DP_EINVAL (bad problem or pointer), DP_ENOTSUP (a move window wider than the LDS
+ * of any sweep tile holds), DP_ENOMEM, DP_EHIP.  The plan must be destroyed with
+ * dp_batch_plan_destroy. */
 typedef struct dp_batch_plan dp_batch_plan;
 
 int dp_batch_plan_create(dp_batch_plan **out, int n, const dp_problem *probs,
