@@ -264,7 +264,9 @@ def batch_compare(dp, torch, reps=2):
             plan.solve(lams, Ps, V1s, pols, **kw)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / reps
-        out[name] = {"ms": round(dt * 1e3, 2), "Gupd_per_s": round(cand / dt / 1e9, 1)}
+        out[name] = {"ms": round(dt * 1e3, 2), "Gupd_per_s": round(cand / dt / 1e9, 1),
+                     # whole solve (sweeps and expectations) against the sweep's VALU peak
+                     "frac_of_valu_peak": round(cand / dt / 1e9 / SWEEP_PEAK_GUPD, 4)}
     out["speedup"] = round(out["looped"]["ms"] / out["batched"]["ms"], 3)
     plan.close()
     return out
@@ -297,6 +299,8 @@ def table3_independent(dp, torch):
         rows.append({"hours": hours, "S": inst.S, "P": P, "T": inst.T, "R": inst.R,
                      "s": round(dt, 4),
                      "sample_action_pairs_per_s": round(inst.S * P * inst.R * inst.T / dt, 1),
+                     "frac_of_valu_peak": round(inst.S * P * inst.R * inst.T / dt / 1e9
+                                                / SWEEP_PEAK_GUPD, 4),
                      "paper_gpu_s": gpu_s, "paper_cpu_s": cpu_s,
                      "paper_gpu_over_this": round(gpu_s / dt, 1)})
         del lam, prob
