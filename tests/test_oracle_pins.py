@@ -393,3 +393,29 @@ def test_ties_resolve_to_smallest_next_state():
     assert np.all(out["V"] == 0.0)
     s = np.arange(12)
     assert np.all(out["policy"] == np.maximum(0, s - 4)[None, None, :])
+
+
+# ---------------------------------------------------------------- tie-break in Algorithm 1's oracle
+def test_algorithm1_policy_index_breaks_ties_to_smallest_next_state():
+    # Hand-built Q tensors (S x P x R) with exact ties: the index returned must be the
+    # largest maximising action on the ascending power grid; -inf (infeasible) is never
+    # chosen and a unique maximum is returned as it is.
+    q = np.array([[[1.0], [3.0], [3.0], [2.0]],           # tie between 1 and 2 -> 2
+                  [[5.0], [-np.inf], [4.0], [-np.inf]],   # unique maximum at 0
+                  [[0.0], [0.0], [0.0], [-np.inf]],       # tie 0, 1, 2; 3 infeasible -> 2
+                  [[7.0], [7.0], [7.0], [7.0]]])          # all tied -> 3
+    assert alg1.policy_index(q)[:, 0].tolist() == [2, 0, 2, 3]
+    # Through Algorithm 1 itself: with zero prices and a zero continuation every feasible
+    # action is worth 0, so the chosen action must be the feasible one with the smallest
+    # next state, computed here from the transition F of Eq. (2) directly.
+    eta, delta = 0.9, 0.1
+    s_hat = alg1.soc_grid(1.0, delta)
+    p_hat, _, _ = alg1.power_grid(0.35, delta, eta)
+    pre = alg1.precompute(s_hat, p_hat, eta)
+    _, Q_all = alg1.stage(pre, p_hat, np.zeros(2), np.array([0.5, 0.5]), np.zeros(s_hat.size))
+    pol = alg1.policy_index(Q_all)
+    for s in range(s_hat.size):
+        nxt = np.array([s_hat[s] + (-p / eta if p >= 0 else -eta * p) for p in p_hat])
+        ok = (nxt >= -1e-9) & (nxt <= s_hat[-1] + 1e-9)
+        best = int(np.flatnonzero(ok)[np.argmin(nxt[ok])])
+        assert pol[s].tolist() == [best, best], (s, pol[s], best)
