@@ -64,7 +64,9 @@ extern "C" {
 
 /* Flags of dp_problem.flags. */
 #define DP_STORE_V_ALL 0x1u  /* V output holds all stages [T+1][K][S] (else V_1 [K][S])   */
-#define DP_VALIDATE    0x2u  /* check P >= 0 and |row sum - 1| <= 1e-6 before solving     */
+#define DP_VALIDATE    0x2u  /* check P >= 0 and |row sum - 1| <= 1e-6 (and, in dp_adjoint,
+                                that every given policy entry is a feasible next state)
+                                before any other device work; synchronises the stream   */
 
 /* Battery on the state-of-charge grid (Sec. III-A): S points 0, delta, ..., (S-1) delta;
  * per-stage move limits w_up (charging) and w_down (discharging) in grid steps. */
@@ -120,7 +122,10 @@ size_t dp_ckpt_bytes(const dp_problem *pb);
 
 /* Backward induction t = T..1 (Eq. (5)-(6), Algorithm 1 with a Markov expectation).
  *   lam     [T][K]     price level of state k at stage t ($/MWh)
- *   P       [T][K][K]  P_t[k][k'] = Pr(state k' at t+1 | state k at t); row k sums to 1
+ *   P       [T][K][K]  P_t[k][k'] = Pr(state k' at t+1 | state k at t); rows are used as
+ *                      given (a row summing to 1 + e weights the continuation by 1 + e);
+ *                      entries >= 0 and row sums within 1e-5 of 1 are assumed by
+ *                      dp_adjoint's fixed-point accumulator, and checked with DP_VALIDATE
  *   v_term  [K][S]     value of ending in (k, s) after stage T; NULL means 0
  *   V       out: [T+1][K][S] (DP_STORE_V_ALL; slice T is v_term) or [K][S] (V_1 only)
  *   policy  out: [T][K][S] int16 next-state index j, or NULL
@@ -151,7 +156,11 @@ size_t dp_adjoint_workspace_bytes(const dp_problem *pb);
  * With ckpt, the re-solve of each segment runs on a library-owned stream of the current
  * device (one per device, created on first use), overlapping the adjoint of the previous
  * segment; it is forked from and joined back into `stream` with events, and calls from
- * several threads are ordered on it.  Requires S <= 8192. */
+ * several threads are ordered on it.
+ * Errors: as dp_solve; with DP_VALIDATE in pb->flags also DP_EBADPROB (a bad row of P)
+ * and DP_EINVAL (a caller-given policy entry outside the feasible move window).  Without
+ * DP_VALIDATE a policy entry outside [0, S) moves no mass (it is never used as an
+ * address); other infeasible entries give the gradient of that (infeasible) policy. */
 int dp_adjoint(const dp_problem *pb, const float *lam, const float *P, const float *v_term,
                const float *V_all, const int16_t *policy, const void *ckpt,
                const float *seed, float *grad_lam, float *grad_P, float *grad_vterm,
@@ -203,6 +212,9 @@ int dp_solve_iid(const dp_iid_problem *pb, const float *lam, const float *prob, 
  * the fastest shape per move-span class, timed at creation), or NULL to use the built-in
  * shapes without tuning (one- and two-wave tiles for move spans up to 256, four waves up
  * to 512, the single solve's choice beyond).
+ * stream: the set-up's device work (zeroing the workspace, uploading the work tables,
+ * timing the candidate shapes) is issued on this stream, after its pending work; the call
+ * synchronises it before returning, so the plan is ready when the call returns.
  * Errors: DP_EINVAL (bad problem or pointer), DP_ENOTSUP (a move window wider than the LDS
  * of any sweep tile holds), DP_ENOMEM, DP_EHIP.  The plan must be destroyed with
  * dp_batch_plan_destroy. */

@@ -173,3 +173,18 @@ def q_values(st, lam_t_k: float, w_row: np.ndarray, s: int) -> np.ndarray:
             g = 0.0
         q[j] = lam_t_k * g - st.c_deg * abs(g) - (st.c_start if d != 0 else 0.0) + w_row[j]
     return q
+
+
+def q_at(st, lam_t, W, k, s, j) -> np.ndarray:
+    """Q(k, s, j) = r(lambda_t[k], j - s) + W[k][j] for index arrays k, s, j (FP64; -inf
+    where j is outside J(s)): the candidate values of given (state, move) pairs, for
+    checking a chosen move against the maximum."""
+    k, s, j = (np.asarray(a, dtype=np.int64) for a in (k, s, j))
+    d = j - s
+    dd = d.astype(np.float64)
+    g = np.where(d > 0, -dd * st.delta / st.eta_c, np.where(d < 0, -dd * st.delta * st.eta_d, 0.0))
+    lam = np.asarray(lam_t, dtype=np.float64)[k]
+    r = lam * g - st.c_deg * np.abs(g) - np.where(d != 0, st.c_start, 0.0)
+    ok = (j >= np.maximum(0, s - st.w_down)) & (j <= np.minimum(st.S - 1, s + st.w_up))
+    wv = np.asarray(W, dtype=np.float64)[k, np.clip(j, 0, st.S - 1)]
+    return np.where(ok, r + wv, -np.inf)

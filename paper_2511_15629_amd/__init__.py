@@ -26,8 +26,15 @@ def _ptr(t: Optional[torch.Tensor]):
 
 
 def _stream(stream=None):
-    s = stream if stream is not None else torch.cuda.current_stream()
-    return ctypes.c_void_p(s.cuda_stream)
+    """The HIP stream for a library call.  A stream other than torch's current one first
+    waits for the current stream, where the binding made its contiguous copies and
+    allocations (and the caller's pending work on the inputs may still run)."""
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    cur = torch.cuda.current_stream(stream.device)
+    if stream != cur:
+        stream.wait_stream(cur)
+    return ctypes.c_void_p(stream.cuda_stream)
 
 
 def _dev_f32(x, name):
@@ -203,8 +210,9 @@ def solve(lam: torch.Tensor, P: torch.Tensor, storage, v_term: Optional[torch.Te
 
 
 def adjoint(lam, P, storage, seed, *, V_all=None, policy=None, ckpt=None, ckpt_every: int = 0,
-            v_term=None, want_vterm: bool = False, stream=None):
-    """Gradients of J = sum(seed * V_1) w.r.t. lam [T, K], P [T, K, K] (and v_term)."""
+            v_term=None, want_vterm: bool = False, validate: bool = False, stream=None):
+    """Gradients of J = sum(seed * V_1) w.r.t. lam [T, K], P [T, K, K] (and v_term).
+    validate=True checks the rows of P and every given policy entry on the device first."""
     lam = _dev_f32(lam, "lam")
     P = _dev_f32(P, "P")
     seed = _dev_f32(seed, "seed")
@@ -215,7 +223,8 @@ def adjoint(lam, P, storage, seed, *, V_all=None, policy=None, ckpt=None, ckpt_e
     dev = lam.device
     _check(P, "P", (T, K, K), torch.float32, dev)
     _check(seed, "seed", (K, S), torch.float32, dev)
-    pb = make_problem(T, K, storage, 0, ckpt_every if ckpt is not None else 0)
+    pb = make_problem(T, K, storage, DP_VALIDATE if validate else 0,
+                      ckpt_every if ckpt is not None else 0)
     L = lib()
     if ckpt is not None:
         _check(ckpt, "ckpt", None, torch.uint8, dev)

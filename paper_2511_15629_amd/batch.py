@@ -56,15 +56,15 @@ class BatchPlan:
               policies=None, *, looped: bool = False, graph: bool = True, stream=None):
         """Batched solve (graph replay); graph=False issues the same launches directly;
         looped=True runs one dp_solve per instance instead."""
+        from . import _stream
         self._check_io(lams, Ps, V1s, policies)
-        s = stream if stream is not None else torch.cuda.current_stream()
+        s = _stream(stream)
         if looped:
             f = lib().dp_batch_solve_looped
         else:
             f = lib().dp_batch_solve if graph else lib().dp_batch_solve_eager
         pol = self._ptrs(policies) if policies is not None else None
-        check(f(self._h, self._ptrs(lams), self._ptrs(Ps), self._ptrs(V1s), pol,
-                ctypes.c_void_p(s.cuda_stream)))
+        check(f(self._h, self._ptrs(lams), self._ptrs(Ps), self._ptrs(V1s), pol, s))
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:

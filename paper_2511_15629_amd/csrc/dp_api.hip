@@ -211,6 +211,7 @@ int run_stages(const dp_problem *pb, int t_lo, int t_hi, const float *lam, const
         if (e != hipSuccess) return hip_fail(e, "contract");
         if ((e = timer_mark(stream, 1, false)) != hipSuccess) return hip_fail(e, "timer");
         a.lam = lam + (size_t)(t - 1) * K;
+        a.P = P + (size_t)(t - 1) * K * K;
         a.off_next = off + (t + 1);
         a.off_cur = off + t;
         a.vnorm = vout;
@@ -229,6 +230,30 @@ int run_stages(const dp_problem *pb, int t_lo, int t_hi, const float *lam, const
         if ((e = timer_mark(stream, 0, false)) != hipSuccess) return hip_fail(e, "timer");
         cur ^= 1;
     }
+    return DP_OK;
+}
+
+// DP_VALIDATE: rows of P (entries >= 0, |row sum - 1| <= 1e-6) and, if given, every
+// policy entry a feasible next state.  Synchronises the stream (the flag is read back).
+int validate_device_inputs(const dp_problem *pb, const float *P, const int16_t *policy,
+                           int *flag, hipStream_t stream)
+{
+    int host[2] = {0, 0};
+    hipError_t e = hipSuccess;
+    for (int c = 0; c < 2 && e == hipSuccess; ++c) {
+        if (c == 1 && !policy) break;
+        e = hipMemcpyAsync(flag, &host[c], sizeof(int), hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess)
+            e = c == 0 ? dpk::launch_validate_P(P, pb->T, pb->K, flag, stream)
+                       : dpk::launch_validate_policy(policy, (size_t)pb->T * pb->K * pb->st.S,
+                                                     pb->st.S, pb->st.w_up, pb->st.w_down, flag,
+                                                     stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(&host[c], flag, sizeof(int), hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    }
+    if (e != hipSuccess) return hip_fail(e, "validate inputs");
+    if (host[0]) return fail(DP_EBADPROB, "a row of P has a negative entry or does not sum to 1");
+    if (host[1]) return fail(DP_EINVAL, "a policy entry is not a feasible next state");
     return DP_OK;
 }
 
@@ -342,14 +367,8 @@ int dp_solve(const dp_problem *pb, const float *lam, const float *P, const float
     if (((uintptr_t)ws & 255) != 0) return fail(DP_EINVAL, "workspace must be 256-byte aligned");
     hipStream_t stream = static_cast<hipStream_t>(stream_);
     if (pb->flags & DP_VALIDATE) {
-        int *flag = reinterpret_cast<int *>(static_cast<char *>(ws) + L.flag);
-        int host = 0;
-        hipError_t e = hipMemcpyAsync(flag, &host, sizeof(int), hipMemcpyHostToDevice, stream);
-        if (e == hipSuccess) e = dpk::launch_validate_P(P, pb->T, pb->K, flag, stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(&host, flag, sizeof(int), hipMemcpyDeviceToHost, stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(stream);
-        if (e != hipSuccess) return hip_fail(e, "validate P");
-        if (host) return fail(DP_EBADPROB, "a row of P has a negative entry or does not sum to 1");
+        rc = validate_device_inputs(pb, P, nullptr, reinterpret_cast<int *>(static_cast<char *>(ws) + L.flag), stream);
+        if (rc != DP_OK) return rc;
     }
     StageOutputs out = {};
     const size_t KS = (size_t)pb->K * pb->st.S;
@@ -368,7 +387,7 @@ int dp_solve(const dp_problem *pb, const float *lam, const float *P, const float
 struct AdjLayout {
     int Spad, G;            // G: stages per grad_P launch (nu_t planes kept for a group)
     int npk;                // stages of P_t^T held repacked for the transport
-    size_t mu, nu, scale, PpT, vseg, polseg, solve_ws, total;
+    size_t mu, nu, scale, flag, PpT, vseg, polseg, solve_ws, total;
 };
 
 static AdjLayout adj_layout(const dp_problem *pb, bool ckpt_mode)
@@ -385,6 +404,7 @@ static AdjLayout adj_layout(const dp_problem *pb, bool ckpt_mode)
     L.mu = o; o += plane;
     L.nu = o; o += (size_t)L.G * plane;
     L.scale = o; o += 256;
+    L.flag = o; o += 256;
     // P_t^T repacked for the transport, up to 32 stages per pack launch (<= 64 MB)
     const size_t pk = sizeof(float) * dpk::packed_P_floats(pb->K);
     L.npk = 32;
@@ -464,7 +484,6 @@ int dp_adjoint(const dp_problem *pb, const float *lam, const float *P, const flo
     int rc = validate_problem(pb);
     if (rc != DP_OK) return rc;
     const int K = pb->K, S = pb->st.S, T = pb->T;
-    if (S > 8192) return fail(DP_ENOTSUP, "adjoint supports S <= 8192 (got %d)", S);
     if (!lam || !P || !seed || !grad_lam || !grad_P) return fail(DP_EINVAL, "lam, P, seed, grad_lam, grad_P must be non-NULL");
     const bool ckpt_mode = (ckpt != nullptr);
     if (ckpt_mode) {
@@ -478,6 +497,11 @@ int dp_adjoint(const dp_problem *pb, const float *lam, const float *P, const flo
     if (((uintptr_t)ws & 255) != 0) return fail(DP_EINVAL, "workspace must be 256-byte aligned");
     hipStream_t stream = static_cast<hipStream_t>(stream_);
     char *base = static_cast<char *>(ws);
+    if (pb->flags & DP_VALIDATE) {
+        rc = validate_device_inputs(pb, P, ckpt_mode ? nullptr : policy,
+                                    reinterpret_cast<int *>(base + L.flag), stream);
+        if (rc != DP_OK) return rc;
+    }
     float *mu = reinterpret_cast<float *>(base + L.mu);
     float *nu = reinterpret_cast<float *>(base + L.nu);
     const size_t plane = align256(sizeof(float) * (size_t)K * L.Spad) / sizeof(float);

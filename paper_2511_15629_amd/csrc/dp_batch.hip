@@ -3,8 +3,9 @@
 // All instances advance together, one batch stage per step: stage tau runs one
 // expectation launch over the contraction tiles of every instance and one sweep launch
 // per tile class over the (instance, price state, SoC tile) blocks of that class.
-// Instance i is at its own stage T_i - tau + 1, so instances of different horizons
-// finish on the same last step.  The whole sequence (an init launch and the per-stage
+// Instance i is at its own stage T_i - tau + 1: every instance starts at tau = 1 with
+// its last stage, and shorter horizons finish earlier (inactive once T_i - tau + 1 < 1).
+// The whole sequence (an init launch and the per-stage
 // launches) is captured once into a HIP graph and replayed; new input/output pointers
 // are written into the device descriptor table before each replay, so the graph never
 // needs re-capture.
@@ -196,7 +197,7 @@ static dpk::SweepShape batch_default_shape(const dp_problem *pb, int span_hi)
     return sh;
 }
 
-static int build_items(dp_batch_plan *p, TileClass &c)
+static int build_items(dp_batch_plan *p, TileClass &c, hipStream_t s)
 {
     c.items.clear();
     c.lds = 0;
@@ -228,15 +229,17 @@ static int build_items(dp_batch_plan *p, TileClass &c)
     if (c.items.empty()) return DP_OK;
     hipError_t e = hipMalloc(&c.d_items, sizeof(dpk::SweepItem) * c.items.size());
     if (e == hipSuccess)
-        e = hipMemcpy(c.d_items, c.items.data(), sizeof(dpk::SweepItem) * c.items.size(),
-                      hipMemcpyHostToDevice);
+        e = hipMemcpyAsync(c.d_items, c.items.data(), sizeof(dpk::SweepItem) * c.items.size(),
+                           hipMemcpyHostToDevice, s);
+    // the host table is reused or freed after this call returns
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "batch item table");
     return DP_OK;
 }
 
 // Time the class's sweep over a few stages with each candidate shape on the plan's own
-// workspace (values are irrelevant to the cost); keep the fastest.
-static int autotune_class(dp_batch_plan *p, TileClass &c, const float *zeros_lam)
+// workspace (values are irrelevant to the cost), on stream s; keep the fastest.
+static int autotune_class(dp_batch_plan *p, TileClass &c, const float *zeros_lam, hipStream_t s)
 {
     double best_us = 1e30;
     dpk::SweepShape best = c.sh;
@@ -249,9 +252,10 @@ static int autotune_class(dp_batch_plan *p, TileClass &c, const float *zeros_lam
         p->hstage[i].pol = nullptr;
         p->hstage[i].V1 = nullptr;
     }
-    hipError_t e = hipMemcpy(p->ddesc, p->hstage, sizeof(dpk::BatchDesc) * p->n, hipMemcpyHostToDevice);
+    hipError_t e = hipMemcpyAsync(p->ddesc, p->hstage, sizeof(dpk::BatchDesc) * p->n,
+                                  hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "tune descriptors");
-    e = dpk::launch_batched_init(p->ddesc, p->n, p->cap);
+    e = dpk::launch_batched_init(p->ddesc, p->n, s);
     if (e != hipSuccess) return hip_fail(e, "tune init");
     hipEvent_t e0, e1;
     if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(e, "tune event");
@@ -264,24 +268,27 @@ static int autotune_class(dp_batch_plan *p, TileClass &c, const float *zeros_lam
         TileClass trial;
         trial.sh = cand;
         trial.inst = c.inst;
-        if ((rc = build_items(p, trial)) != DP_OK) break;
+        if ((rc = build_items(p, trial, s)) != DP_OK) break;
         // tau = 1 keeps every instance active (stage T_i); the W buffer holds zeros
         double t_min = 1e30;
         // the minimum over 5 timed repeats of 6 stages (after one warm-up): single launches
         // of the smaller classes last tens of microseconds, where one repeat is noisy
         for (int rep = 0; rep < 6 && rc == DP_OK; ++rep) {
-            e = hipEventRecord(e0, p->cap);
+            e = hipEventRecord(e0, s);
             for (int st = 0; st < 6 && e == hipSuccess; ++st)
                 e = dpk::launch_batched_sweep(p->ddesc, trial.d_items, (int)trial.items.size(), 1,
-                                              trial.sh, trial.lds, p->cap);
-            if (e == hipSuccess) e = hipEventRecord(e1, p->cap);
+                                              trial.sh, trial.lds, s);
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
             float ms = 0.f;
             if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
             if (e != hipSuccess) rc = hip_fail(e, "tune timing");
             if (rep > 0) t_min = std::min(t_min, ms * 1e3 / 6.0);
         }
-        if (trial.d_items) (void)hipFree(trial.d_items);
+        if (trial.d_items) {
+            (void)hipStreamSynchronize(s);    // the timed launches read the table
+            (void)hipFree(trial.d_items);
+        }
         if (rc != DP_OK) break;
         if (t_min < best_us) {
             best_us = t_min;
@@ -333,7 +340,7 @@ int dp_batch_plan_create(dp_batch_plan **out, int n, const dp_problem *probs,
     if (!out) return fail(DP_EINVAL, "out is NULL");
     *out = nullptr;
     if (n < 1 || !probs) return fail(DP_EINVAL, "need n >= 1 problems");
-    (void)stream_;
+    hipStream_t s = static_cast<hipStream_t>(stream_);
     dp_batch_plan *p = new (std::nothrow) dp_batch_plan;
     if (!p) return fail(DP_ENOMEM, "plan allocation");
     p->n = n;
@@ -371,7 +378,7 @@ int dp_batch_plan_create(dp_batch_plan **out, int n, const dp_problem *probs,
     const size_t zoff = total;
     total += 256 + sizeof(float) * (size_t)Kmax * (size_t)p->Tmax;   // zero prices for tuning
     hipError_t e = hipMalloc(&p->ws, total);
-    if (e == hipSuccess) e = hipMemset(p->ws, 0, total);
+    if (e == hipSuccess) e = hipMemsetAsync(p->ws, 0, total, s);
     if (e == hipSuccess) e = hipMalloc(&p->ddesc, sizeof(dpk::BatchDesc) * n);
     if (e == hipSuccess) e = hipHostMalloc(&p->hstage, sizeof(dpk::BatchDesc) * n);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
@@ -437,15 +444,16 @@ int dp_batch_plan_create(dp_batch_plan **out, int n, const dp_problem *probs,
     if (!citems.empty()) {
         e = hipMalloc(&p->d_citems, sizeof(dpk::ContractItem) * citems.size());
         if (e == hipSuccess)
-            e = hipMemcpy(p->d_citems, citems.data(), sizeof(dpk::ContractItem) * citems.size(),
-                          hipMemcpyHostToDevice);
+            e = hipMemcpyAsync(p->d_citems, citems.data(), sizeof(dpk::ContractItem) * citems.size(),
+                               hipMemcpyHostToDevice, s);
     }
     if (e == hipSuccess && !pitems.empty()) {
         e = hipMalloc(&p->d_pitems, sizeof(dpk::ContractItem) * pitems.size());
         if (e == hipSuccess)
-            e = hipMemcpy(p->d_pitems, pitems.data(), sizeof(dpk::ContractItem) * pitems.size(),
-                          hipMemcpyHostToDevice);
+            e = hipMemcpyAsync(p->d_pitems, pitems.data(), sizeof(dpk::ContractItem) * pitems.size(),
+                               hipMemcpyHostToDevice, s);
     }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);     // host tables are freed on return
     if (e != hipSuccess) {
         destroy_plan(p);
         return hip_fail(e, "expectation item table");
@@ -470,7 +478,7 @@ int dp_batch_plan_create(dp_batch_plan **out, int n, const dp_problem *probs,
             if (fits_all) c.sh = it->second;
         }
         if (tune_cache && (it == cached.end() || !fits_all)) {
-            rc = autotune_class(p, c, zeros_lam);
+            rc = autotune_class(p, c, zeros_lam, s);
             if (rc != DP_OK) break;
             append_cache(tune_cache, kv.first, c.sh, c.tuned_us);
         }
@@ -500,7 +508,7 @@ int dp_batch_plan_create(dp_batch_plan **out, int n, const dp_problem *probs,
         p->classes = merged;
         for (auto &c : p->classes) {
             c.d_items = nullptr;
-            if ((rc = build_items(p, c)) != DP_OK) break;
+            if ((rc = build_items(p, c, s)) != DP_OK) break;
         }
     }
     if (rc == DP_OK) {
@@ -522,6 +530,10 @@ int dp_batch_plan_create(dp_batch_plan **out, int n, const dp_problem *probs,
     if (rc != DP_OK) {
         destroy_plan(p);
         return rc;
+    }
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) {
+        destroy_plan(p);
+        return hip_fail(e, "plan set-up");
     }
     // description
     char buf[512];

@@ -16,6 +16,7 @@ struct SweepArgs {
     const float *W;          // [K][ldw] expectation W_t; W[0] is the stage's normalisation
     int ldw;
     const float *lam;        // [K]
+    const float *P;          // [K][K] P_t, for the row sums rho_k (nullable: rows sum to 1)
     int K, S, w_up, w_down;
     Payoff pay;
     const double *off_next;  // C_{t+1}
@@ -134,5 +135,7 @@ hipError_t launch_copy_rows(const float *src, int lds, float *dst, int ldd, int 
                             hipStream_t stream);
 hipError_t launch_fill(float *dst, size_t n, float v, hipStream_t stream);
 hipError_t launch_validate_P(const float *P, int T, int K, int *flag, hipStream_t stream);
+hipError_t launch_validate_policy(const int16_t *pol, size_t n, int S, int w_up, int w_down,
+                                  int *flag, hipStream_t stream);
 
 }  // namespace dpk

@@ -219,6 +219,18 @@ hipError_t launch_contract_packed(const float *Ap, const float *B, int ldb, floa
 // from the same operands, so the equality is exact, and "first chunk, then first move
 // within it" is the smallest next state attaining the maximum.
 // ------------------------------------------------------------------------------------
+// Sum of the K entries of a row of P_t in FP64, the same in every wave and every kernel:
+// lane l adds entries l, l + 64, ... in ascending order, then a xor butterfly (each step
+// adds the same two operands on both lanes, so every lane ends with the same bits).
+__device__ __forceinline__ double row_sum_f64(const float *__restrict__ row, int K, int lane)
+{
+    double acc = 0.0;
+    for (int c = lane; c < K; c += 64) acc += (double)row[c];
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) acc += __shfl_xor(acc, m);
+    return acc;
+}
+
 // Barrier between a tile's LDS phases: the block's, or for a one-wave tile only a code
 // motion fence (one wave's LDS operations complete in program order).
 template <int NW>
@@ -259,7 +271,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
     // stage's normalisation constant W_t[0][0] and the offset C_{t+1} (for the epilogue).
     const float *Wk = a.W + (size_t)k * a.ldw;
     float lam = 0.0f, shift = 0.0f;
-    double off_next = 0.0;
+    double off_next = 0.0, rsum = 1.0;
     for (int i4 = 0; i4 < nwl; i4 += 4 * NW * 64) {     // nwl > 0: at least one pass
         float w[4];
 #pragma unroll
@@ -273,6 +285,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
             lam = a.lam[k];
             shift = a.W[0];
             off_next = a.off_next[0];
+            if (a.P) rsum = row_sum_f64(a.P + (size_t)k * a.K, a.K, tid & 63);
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -337,6 +350,10 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
     sweep_sync<NW>();
 
     const double Ct = off_next + (double)shift;   // shift = W_t[0][0], the normalisation
+    // W_t was formed from the normalised V_{t+1}; its true value adds rho_k C_{t+1}, of which
+    // C_{t+1} is carried by the offset and (rho_k - 1) C_{t+1} goes into the row (exactly 0,
+    // and skipped, when the row sums to 1)
+    const double corr = (rsum - 1.0) * off_next;
     for (int o = tid; o < TS; o += NW * 64) {
         const int s = s0 + o;
         if (s >= S) break;
@@ -357,7 +374,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
             if (x == bv) arg = d;
         }
         const int j = s + dlo + bc * D + arg;
-        const float vn = bv - shift;
+        const float vn = corr == 0.0 ? bv - shift : (float)((double)(bv - shift) + corr);
         const size_t idx = (size_t)k * S + s;
         a.vnorm[(size_t)k * a.ldv + s] = vn;
         // outputs the next launch does not read go out as non-temporal stores
@@ -703,12 +720,15 @@ __global__ __launch_bounds__(1024) void iid_stage_kernel(IidArgs a)
     }
     __syncthreads();
     const double Ct = off_next + (double)shift;
+    // the expectation of the offset C_t is (sum_r pi_r) C_t: C_t is carried by the offset,
+    // (sum_r pi_r - 1) C_t goes into the values (exactly 0, and skipped, when pi sums to 1)
+    const double corr = (row_sum_f64(pr, R, tid & 63) - 1.0) * off_next;
     for (int o = tid; o < TS; o += nth) {
         const int s = s0 + o;
         if (s >= S) continue;
         float acc = part[o];
         for (int p = 1; p < NP; ++p) acc += part[p * TS + o];
-        const float vn = acc - shift;
+        const float vn = corr == 0.0 ? acc - shift : (float)((double)(acc - shift) + corr);
         a.Vout[s] = vn;
         if (a.vabs) a.vabs[s] = (float)((double)vn + Ct);
     }
@@ -771,6 +791,7 @@ __global__ __launch_bounds__(NW * 64 * tiles_per_block<NW>()) void batched_sweep
     a.W = d.W;
     a.ldw = d.ld;
     a.lam = d.lam + (size_t)(t - 1) * d.K;
+    a.P = d.P ? d.P + (size_t)(t - 1) * d.K * d.K : nullptr;
     a.K = d.K;
     a.S = d.S;
     a.w_up = d.w_up;
@@ -1076,8 +1097,12 @@ hipError_t launch_init_terminal(const float *src, const double *src_off, int K, 
 // butterfly within each wave and the waves' sums in wave order.  One block per price
 // state; the block's policy and mass loads (up to PF per thread) and the scale are issued
 // before the accumulator is cleared, so the block waits for one memory round trip.
+// The accumulator covers PUSH_JC next states at a time (128 KB of LDS): rows longer than
+// that take one pass per chunk of next states, each over every s.  A policy entry outside
+// [0, S) adds nothing (memory safety; dp_adjoint with DP_VALIDATE rejects such policies).
 // ------------------------------------------------------------------------------------
 constexpr int PF = 8;
+constexpr int PUSH_JC = 16384;
 
 __global__ __launch_bounds__(1024) void pushforward_kernel(const float *__restrict__ mu,
                                                            int ldm,
@@ -1088,7 +1113,7 @@ __global__ __launch_bounds__(1024) void pushforward_kernel(const float *__restri
                                                            float *__restrict__ grad_lam)
 {
     extern __shared__ float4 smem4[];
-    unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem4);   // [S]
+    unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem4);   // [min(S, JC)]
     __shared__ float red[16];
     const int k = blockIdx.x;
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -1103,30 +1128,38 @@ __global__ __launch_bounds__(1024) void pushforward_kernel(const float *__restri
         mv[u] = s < S ? mk[s] : 0.0f;
     }
     const double sc = scale[0];
-    for (int i = tid; i < S; i += nt) acc[i] = 0ull;
-    __syncthreads();
+    const double inv = 1.0 / sc;
     float gl = 0.0f;
+    for (int j0 = 0; j0 < S; j0 += PUSH_JC) {
+        const int jn = min(PUSH_JC, S - j0);
+        for (int i = tid; i < jn; i += nt) acc[i] = 0ull;
+        __syncthreads();
 #pragma unroll
-    for (int u = 0; u < PF; ++u) {
-        const int s = tid + u * nt;
-        if (s < S) {
-            gl = fmaf(mv[u], move_energy(jv[u] - s, pay), gl);
-            atomicAdd(&acc[jv[u]], (unsigned long long)llrint((double)mv[u] * sc));
+        for (int u = 0; u < PF; ++u) {
+            const int s = tid + u * nt;
+            if (s < S) {
+                if (j0 == 0) gl = fmaf(mv[u], move_energy(jv[u] - s, pay), gl);
+                const unsigned jr = (unsigned)(jv[u] - j0);
+                if (jr < (unsigned)jn)
+                    atomicAdd(&acc[jr], (unsigned long long)llrint((double)mv[u] * sc));
+            }
         }
-    }
-    for (int s = tid + PF * nt; s < S; s += nt) {      // beyond the preloaded elements
-        const int j = pk[s];
-        const float m = mk[s];
-        gl = fmaf(m, move_energy(j - s, pay), gl);
-        atomicAdd(&acc[j], (unsigned long long)llrint((double)m * sc));
+        for (int s = tid + PF * nt; s < S; s += nt) {      // beyond the preloaded elements
+            const int j = pk[s];
+            const float m = mk[s];
+            if (j0 == 0) gl = fmaf(m, move_energy(j - s, pay), gl);
+            const unsigned jr = (unsigned)(j - j0);
+            if (jr < (unsigned)jn) atomicAdd(&acc[jr], (unsigned long long)llrint((double)m * sc));
+        }
+        __syncthreads();
+        for (int i = tid; i < jn; i += nt)
+            nu[(size_t)k * ldn + j0 + i] = (float)((double)(long long)acc[i] * inv);
+        __syncthreads();                                    // acc is cleared next pass
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) gl += __shfl_xor(gl, o);
     if ((tid & 63) == 0) red[tid >> 6] = gl;
     __syncthreads();
-    const double inv = 1.0 / sc;
-    for (int i = tid; i < S; i += nt)
-        nu[(size_t)k * ldn + i] = (float)((double)(long long)acc[i] * inv);
     if (tid == 0) {
         float sum = red[0];
         for (int w = 1; w < (nt >> 6); ++w) sum += red[w];
@@ -1138,10 +1171,33 @@ hipError_t launch_pushforward(const float *mu, int ldm, const int16_t *pol, int 
                               Payoff pay, const double *scale, float *nu, int ldn,
                               float *grad_lam, hipStream_t stream)
 {
-    const size_t lds = sizeof(unsigned long long) * (size_t)S;
+    const size_t lds = sizeof(unsigned long long) * (size_t)min(S, PUSH_JC);
     const int nt = S >= 4096 ? 1024 : (S >= 1024 ? 512 : 256);
     hipLaunchKernelGGL(pushforward_kernel, dim3(K), dim3(nt), lds, stream, mu, ldm, pol, K, S,
                        pay, scale, nu, ldn, grad_lam);
+    return hipGetLastError();
+}
+
+// Policy check for dp_adjoint with DP_VALIDATE: every entry a feasible next state,
+// max(0, s - w_down) <= j <= min(S - 1, s + w_up); *flag is set to 1 otherwise.
+__global__ void validate_policy_kernel(const int16_t *__restrict__ pol, size_t n, int S,
+                                       int w_up, int w_down, int *flag)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const int s = (int)(i % S), j = pol[i];
+        if (j < max(0, s - w_down) || j > min(S - 1, s + w_up)) atomicOr(flag, 1);
+    }
+}
+
+hipError_t launch_validate_policy(const int16_t *pol, size_t n, int S, int w_up, int w_down,
+                                  int *flag, hipStream_t stream)
+{
+    int blocks = (int)((n + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(validate_policy_kernel, dim3(blocks), dim3(256), 0, stream, pol, n, S,
+                       w_up, w_down, flag);
     return hipGetLastError();
 }
 

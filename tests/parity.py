@@ -51,18 +51,24 @@ def check_solve(st, lam, P, V_gpu_all, pol_gpu, or_out, label=""):
 STATS = {"mismatch": 0, "max_regret": 0.0}
 
 
-def _mismatch(st, lam_t, P_t, v_next_or, v_or, pol_gpu, pol_or, label):
-    _, _, W = oracle.stage(st, lam_t, P_t, v_next_or, want_w=True)
+def _mismatch(st, lam_t, P_t, v_next_or, v_or, pol_gpu, pol_or, label, W=None):
+    if W is None:
+        _, _, W = oracle.stage(st, lam_t, P_t, v_next_or, want_w=True)
     scale = max(float(np.max(np.abs(v_or))), 1e-30)
     tol = RTOL * scale
-    mism = np.argwhere(pol_gpu != pol_or)
-    STATS["mismatch"] += int(mism.shape[0])
-    for k, s in mism:
-        q = oracle.q_values(st, float(lam_t[k]), W[k], int(s))
-        j = int(pol_gpu[k, s])
-        assert np.isfinite(q[j]), f"{label}: GPU chose infeasible j={j} at k={k}, s={s}"
-        assert q[j] >= v_or[k, s] - tol, (
-            f"{label}: policy mismatch at k={k} s={s}: gpu j={j} (Q={q[j]:.9g}) vs "
-            f"oracle j={int(pol_or[k, s])} (V={v_or[k, s]:.9g})")
-        STATS["max_regret"] = max(STATS["max_regret"], float(v_or[k, s] - q[j]) / scale)
-    return int(mism.shape[0])
+    k, s = np.nonzero(pol_gpu != pol_or)
+    STATS["mismatch"] += int(k.size)
+    if k.size == 0:
+        return 0
+    j = pol_gpu[k, s].astype(np.int64)
+    q = oracle.q_at(st, lam_t, W, k, s, j)
+    bad = ~np.isfinite(q)
+    assert not bad.any(), (f"{label}: GPU chose an infeasible move at k={k[bad][0]}, "
+                           f"s={s[bad][0]} (j={j[bad][0]})")
+    regret = v_or[k, s] - q
+    i = int(np.argmax(regret))
+    assert regret[i] <= tol, (
+        f"{label}: policy mismatch at k={k[i]} s={s[i]}: gpu j={j[i]} (Q={q[i]:.9g}) vs "
+        f"oracle j={int(pol_or[k[i], s[i]])} (V={v_or[k[i], s[i]]:.9g})")
+    STATS["max_regret"] = max(STATS["max_regret"], float(regret[i]) / scale)
+    return int(k.size)

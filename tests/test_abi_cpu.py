@@ -85,9 +85,13 @@ def test_adjoint_argument_rules(L):
     # both full-storage inputs and a checkpoint: rejected
     rc = L.dp_adjoint(ctypes.byref(pb), 1, 1, None, 1, 1, 1, 1, 1, 1, None, 256, need, None)
     assert rc == -1
-    pb2 = _pb(S=9000)
-    rc = L.dp_adjoint(ctypes.byref(pb2), 1, 1, None, 1, 1, None, 1, 1, 1, None, 256, 1 << 30, None)
-    assert rc == -7
+    # every S up to DP_MAX_S is accepted (the push-forward takes the next states in
+    # chunks); a too-small workspace is still rejected before any device work
+    pb2 = _pb(S=32767)
+    need2 = L.dp_adjoint_workspace_bytes(ctypes.byref(pb2))
+    assert need2 > 0
+    rc = L.dp_adjoint(ctypes.byref(pb2), 1, 1, None, 1, 1, None, 1, 1, 1, None, 256, need2 - 1, None)
+    assert rc == -3
 
 
 def test_checkpoint_size_counts_interior_slots(L):

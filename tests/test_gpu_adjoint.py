@@ -4,6 +4,8 @@ Reference: the FP64 oracle adjoint evaluated under the GPU's policies (the gradi
 the value of a fixed policy set), and central finite differences of the FP64 oracle at
 points where the perturbation changes no policy.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -81,6 +83,18 @@ def test_adjoint_matches_oracle_under_gpu_policy(dp, case):
     assert normwise(g["grad_vterm"].cpu().numpy(), ref["grad_vterm"]) <= RTOL
 
 
+def test_adjoint_with_rows_off_the_simplex_matches_oracle(dp):
+    # rows summing to 1 only within 2e-6: the forward values carry the row sums exactly,
+    # and the gradients are the raw partials of that forward map
+    base = wl.random_small(6, 40, 12, 200, 20, 30, c_start=1.0)
+    inst = dataclasses.replace(base, P=wl.unnormalised_rows(base.P, 2e-6, seed=6))
+    om = np.random.default_rng(6).uniform(0, 1, size=(12, 200)).astype(np.float32)
+    out, g = gpu_forward_backward(dp, inst, om)
+    ref = oracle_under_gpu_policy(inst, out["policy"].cpu().numpy(), om)
+    for key in ("grad_lam", "grad_P", "grad_vterm"):
+        assert normwise(g[key].cpu().numpy(), ref[key]) <= RTOL, key
+
+
 def test_adjoint_full_size_day(dp):
     inst = wl.day_5min_adjoint()
     om = wl.default_seed(inst.K, inst.storage.S)
@@ -124,44 +138,73 @@ def test_adjoint_is_deterministic(dp):
         assert torch.equal(a[key], b[key])
 
 
-def test_adjoint_against_finite_differences(dp):
-    """K=10, S=101, +-25, T=288 sub-instance; h = 2^-10 $/MWh on prices (exact in FP32).
+def fd_checks(inst, om, gl, gP, pol_gpu, *, n_lam=24, n_P=8, min_opt=4, seed=3):
+    """Central differences of FP64 oracle objectives against the GPU gradients.
 
-    Two FP64 references: (a) central differences of the value of the GPU's policy set
-    (J is linear in lam for fixed policies, so the difference quotient is exact), at
-    every sampled point; (b) central differences of the optimal value, at points where
-    neither perturbation changes the optimal policy and the GPU policy equals it.
-    """
-    inst = wl.fd_sub_5min()
+    (a) The value of the GPU's policy set, J_pi(lam, P) = sum om * V1_pi: for fixed policies
+        it is linear in each lam_t[k] and each P_t[k][k'], so the difference quotient is
+        exact; checked at every sampled point, for prices and for single entries of P
+        (raw partials: the perturbed row is not renormalised).
+    (b) The optimal value J*(lam), at price points where it is differentiable along the
+        perturbation and the GPU's gradient is the derivative of J*: the oracle's optimal
+        policy stays optimal at lam +- h (J* = J_pi_or there, to rounding), and the GPU's
+        policies give the same derivative at that point as the oracle's (the two policy
+        sets agree wherever the occupation measure reaching (t, k) has mass).  Points
+        near t = 1 are included, where that measure is concentrated on few states.
+    Returns the number of points compared in (b)."""
     st = inst.storage
-    om = wl.default_seed(inst.K, st.S)
-    out, g = gpu_forward_backward(dp, inst, om)
-    gl = g["grad_lam"].cpu().numpy()
-    pol_gpu = out["policy"].cpu().numpy()
     base = oracle.solve(st, inst.lam, inst.P)
-    same_policy = np.array_equal(pol_gpu, base["policy"])
-    rng = np.random.default_rng(3)
+    pol_or = base["policy"]
+    om64 = om.astype(np.float64)
+    g_or = oracle.adjoint(st, inst.lam, inst.P, base["V"], pol_or, om64)["grad_lam"]
+    g_gp = oracle_under_gpu_policy(inst, pol_gpu, om)["grad_lam"]
+    J = lambda lam, P, pol: float((om64 * oracle.policy_value(st, lam, P, pol)).sum())
+    rng = np.random.default_rng(seed)
     h = 2.0 ** -10
     tol = 1e-4 * max(1.0, float(np.max(np.abs(gl))))
+    scale = max(abs(J(inst.lam, inst.P, pol_or)), 1.0)
     n_opt = 0
-    for _ in range(24):
-        t, k = int(rng.integers(0, inst.T)), int(rng.integers(0, inst.K))
-        jp, jo = [], []
-        stable = True
+    for n in range(n_lam):
+        t = int(rng.integers(0, 4)) if n % 3 == 0 else int(rng.integers(0, inst.T))
+        k = int(rng.integers(0, inst.K))
+        jp, jo, jor = [], [], []
         for sgn in (1, -1):
             lam2 = inst.lam.copy()
             lam2[t, k] = np.float32(float(lam2[t, k]) + sgn * h)
-            jp.append(float((om * oracle.policy_value(st, lam2, inst.P, pol_gpu)).sum()))
-            o = oracle.solve(st, lam2, inst.P, keep_all=False)
-            stable &= np.array_equal(o["policy"], base["policy"])
-            jo.append(float((om * o["V1"]).sum()))
+            jp.append(J(lam2, inst.P, pol_gpu))
+            jor.append(J(lam2, inst.P, pol_or))
+            jo.append(float((om64 * oracle.solve(st, lam2, inst.P, keep_all=False)["V1"]).sum()))
         fd_pol = (jp[0] - jp[1]) / (2 * h)
-        assert abs(fd_pol - gl[t, k]) <= tol, (t, k, fd_pol, gl[t, k])
-        if stable and same_policy:
+        assert abs(fd_pol - gl[t, k]) <= tol, ("lam", t, k, fd_pol, gl[t, k])
+        stays_optimal = all(abs(a - b) <= 1e-12 * scale for a, b in zip(jo, jor))
+        same_derivative = abs(g_or[t, k] - g_gp[t, k]) <= 1e-12 * max(1.0, abs(g_or[t, k]))
+        if stays_optimal and same_derivative:
             fd_opt = (jo[0] - jo[1]) / (2 * h)
-            assert abs(fd_opt - gl[t, k]) <= tol, (t, k, fd_opt, gl[t, k])
+            assert abs(fd_opt - gl[t, k]) <= tol, ("opt", t, k, fd_opt, gl[t, k])
             n_opt += 1
-    print(f"FD points vs optimal value: {n_opt}; GPU policy equals oracle policy: {same_policy}")
+    tolP = 1e-4 * max(1.0, float(np.max(np.abs(gP))))
+    hP = 2.0 ** -12          # P +- hP is exact in FP32 for entries on the 2^-24 grid
+    for _ in range(n_P):
+        t, k, kp = (int(rng.integers(0, m)) for m in (inst.T, inst.K, inst.K))
+        jp = []
+        for sgn in (1, -1):
+            P2 = inst.P.copy()
+            P2[t, k, kp] = np.float32(float(P2[t, k, kp]) + sgn * hP)
+            jp.append(J(inst.lam, P2, pol_gpu))
+        fd = (jp[0] - jp[1]) / (2 * hP)
+        assert abs(fd - gP[t, k, kp]) <= tolP, ("P", t, k, kp, fd, gP[t, k, kp])
+    assert n_opt >= min_opt, f"only {n_opt} points where the optimal value is differentiable"
+    return n_opt
+
+
+def test_adjoint_against_finite_differences(dp):
+    """K=10, S=101, +-25, T=288 sub-instance; h = 2^-10 $/MWh on prices, 2^-12 on P."""
+    inst = wl.fd_sub_5min()
+    om = wl.default_seed(inst.K, inst.storage.S)
+    out, g = gpu_forward_backward(dp, inst, om)
+    n_opt = fd_checks(inst, om, g["grad_lam"].cpu().numpy(), g["grad_P"].cpu().numpy(),
+                      out["policy"].cpu().numpy())
+    print(f"FD points compared with the optimal value's derivative: {n_opt}")
 
 
 def test_autograd_function_matches_direct_adjoint(dp):
@@ -177,3 +220,48 @@ def test_autograd_function_matches_direct_adjoint(dp):
                        policy=out["policy"])
         assert torch.equal(gl, d["grad_lam"]) and torch.equal(gP, d["grad_P"])
         assert torch.equal(V1.detach(), out["V"][0])
+
+
+@pytest.mark.parametrize("S", [16385, 32767])
+def test_adjoint_beyond_one_accumulator_chunk_matches_oracle(dp, S):
+    # the push-forward holds 16384 next states in LDS at a time: a row of 16385 takes two
+    # passes (the second of one state), the largest grid two passes of 16384 and 16383;
+    # moves of +-300 cross the chunk boundary
+    inst = wl.random_small(20 + S % 7, 3, 2, S, 300, 300, delta=0.001, c_start=0.5)
+    om = np.random.default_rng(S).uniform(0, 1, size=(2, S)).astype(np.float32)
+    out, g = gpu_forward_backward(dp, inst, om)
+    ref = oracle_under_gpu_policy(inst, out["policy"].cpu().numpy(), om)
+    for key in ("grad_lam", "grad_P", "grad_vterm"):
+        assert normwise(g[key].cpu().numpy(), ref[key]) <= RTOL, key
+
+
+def test_validation_rejects_infeasible_policies(dp):
+    inst = wl.random_small(14, 5, 3, 50, 4, 6)
+    lam, P = dev(inst.lam), dev(inst.P)
+    out = dp.solve(lam, P, inst.storage, store_all=True)
+    seed = torch.rand(3, 50, device="cuda")
+    ok = dp.adjoint(lam, P, inst.storage, seed, V_all=out["V"], policy=out["policy"], validate=True)
+    bad = out["policy"].clone()
+    bad[2, 1, 10] = 10 + 5          # beyond w_up = 4
+    with pytest.raises(dp.DPError) as e:
+        dp.adjoint(lam, P, inst.storage, seed, V_all=out["V"], policy=bad, validate=True)
+    assert e.value.code == -1 and "feasible" in str(e.value)
+    bad[2, 1, 10] = -1              # outside [0, S): no mass moves, nothing is written there
+    g = dp.adjoint(lam, P, inst.storage, seed, V_all=out["V"], policy=bad)
+    torch.cuda.synchronize()
+    assert torch.isfinite(g["grad_P"]).all() and torch.isfinite(ok["grad_P"]).all()
+
+
+def test_side_stream_adjoint_equals_current_stream(dp):
+    inst = wl.random_small(15, 12, 8, 300, 30, 30, c_start=1.0)
+    om = np.random.default_rng(2).uniform(0, 1, size=(8, 300)).astype(np.float32)
+    _, ref = gpu_forward_backward(dp, inst, om)
+    side = torch.cuda.Stream()
+    lam, P, seed = dev(inst.lam), dev(inst.P), dev(om)      # copies queued on the current stream
+    out = dp.solve(lam, P, inst.storage, store_all=True, stream=side)
+    g = dp.adjoint(lam, P, inst.storage, seed, V_all=out["V"], policy=out["policy"],
+                   want_vterm=True, stream=side)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    for key in ("grad_lam", "grad_P", "grad_vterm"):
+        assert torch.equal(g[key], ref[key]), key

@@ -136,3 +136,21 @@ def test_maximum_grid_sampled_stages(dp):
         scale = max(float(np.max(np.abs(v_or))), float(np.max(np.abs(v_gpu))), 1e-30)
         assert float(np.max(np.abs(v_gpu[rows] - v_or))) <= RTOL * scale, t
         check_policy(out["policy"][t - 1].cpu().numpy()[:, rows], Q_all, v_or)
+
+
+def test_probabilities_off_the_simplex_long_horizon(dp):
+    """Sample probabilities summing to 1 only within 2e-6 over 2000 stages: the offset
+    carried between stages is weighted by the probability sum, as the expectation is."""
+    T, R, S, delta, eta, p_bar = 2000, 20, 101, 0.04, math.sqrt(0.85), 1.0
+    lam, prob = wl.iid_prices(T, R, seed=5)
+    prob = wl.unnormalised_rows(prob, 2e-6, seed=5)
+    assert np.abs(prob.astype(np.float64).sum(-1) - 1.0).max() > 1e-6
+    s_hat, p_hat, _, _ = grid(S, delta, eta, p_bar)
+    out = dp.solve_independent(dev(lam), dev(prob), S, delta, eta, p_bar, store_all=True)
+    torch.cuda.synchronize()
+    V = out["V"].cpu().numpy()
+    pre = alg1.precompute(s_hat, p_hat, float(np.float32(eta)))
+    Vo = np.zeros(S)
+    for t in range(T, 0, -1):
+        Vo, _ = alg1.stage(pre, p_hat, lam[t - 1], prob[t - 1], Vo)
+        assert normwise(V[t - 1], Vo) <= RTOL, t

@@ -419,3 +419,22 @@ def test_algorithm1_policy_index_breaks_ties_to_smallest_next_state():
         ok = (nxt >= -1e-9) & (nxt <= s_hat[-1] + 1e-9)
         best = int(np.flatnonzero(ok)[np.argmin(nxt[ok])])
         assert pol[s].tolist() == [best, best], (s, pol[s], best)
+
+
+# ---------------------------------------------------------------- candidate lookup used by the near-tie rule
+def test_candidate_lookup_attains_the_stage_maximum():
+    # q_at(k, s, j) must equal the stage value at the oracle's own argmax, never exceed it
+    # at any feasible move, and be -inf exactly outside J(s).
+    inst = _rand(5, 3, 4, 50, 6, 7, c_start=1.0, lam_lo=-60.0)
+    st = inst.storage
+    v = np.random.default_rng(0).normal(size=(4, 50))
+    V, pol, W = oracle.stage(st, inst.lam[0], inst.P[0], v, want_w=True)
+    k, s = np.meshgrid(np.arange(4), np.arange(50), indexing="ij")
+    k, s = k.ravel(), s.ravel()
+    np.testing.assert_allclose(oracle.q_at(st, inst.lam[0], W, k, s, pol[k, s]), V[k, s],
+                               rtol=0, atol=1e-12)
+    for j in range(50):
+        q = oracle.q_at(st, inst.lam[0], W, k, s, np.full_like(k, j))
+        feas = (j >= s - st.w_down) & (j <= s + st.w_up)
+        assert np.all(np.isinf(q[~feas])) and np.all(np.isfinite(q[feas]))
+        assert np.all(q[feas] <= V[k, s][feas] + 1e-12)

@@ -125,6 +125,15 @@ def quantize_rows(P: np.ndarray) -> np.ndarray:
     return out
 
 
+def unnormalised_rows(P: np.ndarray, rel: float, *, seed: int) -> np.ndarray:
+    """Rows of P scaled by independent factors 1 + U(-rel, rel), rounded to FP32: rows
+    that no longer sum to 1 exactly (as estimated or float-rounded transition matrices
+    do), for checking that a solver does not rely on exact unit row sums."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    fac = 1.0 + rng.uniform(-rel, rel, size=P.shape[:-1] + (1,))
+    return f32(np.asarray(P, dtype=np.float64) * fac)
+
+
 def f32(a) -> np.ndarray:
     return np.asarray(a, dtype=np.float64).astype(np.float32)
 
