@@ -1,8 +1,10 @@
 #!/usr/bin/env python
 """Throughput of the GPU backward induction on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload day_5min]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload year_hourly]
 
+The default workload is the year-long hourly solve (T = 8760 stages, K = 50 price states,
+S = 2001 SoC points, moves of +-500 steps, a 5 $ start cost): the largest single solve.
 A step is one full backward induction of the workload: for every stage the expectation
 W_t = P_t V_{t+1} (MFMA) and the max-plus Bellman sweep with argmax, writing V_1 and all
 int16 policies to HBM.  The metric is feasible state-action updates per second (the
@@ -13,9 +15,12 @@ carries:
                 its average launch time, measured with HIP events on the solve's stream
                 in a second pass of the same steps right after the timed ones, against
                 the VALU issue bound (1.5 lane-instructions per candidate);
-  cpu_baseline  the FP64 oracle timed on this host's cores on a bounded sample;
-  extra         the year-long hourly solve, the adjoint/value time ratio and the
-                batched/looped comparison, each on the same GPU.
+  cpu_baseline  the FP64 oracle timed on this host's cores on a bounded sample of the
+                same workload (its last stages);
+  extra         the five-minute day solve, the adjoint/value time ratio and the
+                batched/looped comparison, each on the same GPU, the paper-mode Table 3
+                shapes, and CPU timings of the oracle and of Algorithm 1 in NumPy on the
+                smaller workloads.
 """
 from __future__ import annotations
 
@@ -100,11 +105,12 @@ class ClockSampler:
 
 
 def timed_solves(dp, torch, inst, steps, warmup, clock=None):
-    """Wall time per step over `steps` solves (no instrumentation), then the same number
-    of identical solves with HIP event pairs (created without the system-scope fence) on
-    the solve's stream around every sweep and expectation launch; event packets between
-    launches slow the steps down, so they are kept out of the timed steps.  The clock
-    sampler, if given, runs during the event-timed solves only."""
+    """Wall time per step over `steps` solves (no instrumentation), then identical solves
+    with HIP event pairs (created without the system-scope fence) on the solve's stream
+    around every sweep and expectation launch, as many solves as keep the event count
+    within about 20k (at least one); event packets between launches slow the steps down, so they are kept
+    out of the timed steps.  The clock sampler, if given, runs during the event-timed
+    solves only."""
     lam = torch.from_numpy(inst.lam).cuda()
     P = torch.from_numpy(inst.P).cuda()
     solver = dp.Solver(lam, P, inst.storage, store_all=False, policy=True)
@@ -119,7 +125,7 @@ def timed_solves(dp, torch, inst, steps, warmup, clock=None):
     dp.lib().dp_set_timing(2)
     import contextlib
     with clock if clock is not None else contextlib.nullcontext():
-        for _ in range(steps):
+        for _ in range(max(1, min(steps, 10000 // inst.T))):
             solver.run()
         torch.cuda.synchronize()
     timing = dp.kernel_timing()
@@ -129,19 +135,23 @@ def timed_solves(dp, torch, inst, steps, warmup, clock=None):
 
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-TRAFFIC_FILE = os.path.join(HERE, "profiles", "sweep_traffic_day_5min.txt")
 KERNEL_SOURCE = os.path.join(HERE, "paper_2511_15629_amd", "csrc", "dp_kernels.hip")
 
 
+def traffic_file(workload: str) -> str:
+    return os.path.join(HERE, "profiles", f"sweep_traffic_{workload}.txt")
+
+
 def measured_traffic(workload: str):
-    """HBM bytes per sweep launch from the committed counter summary (two rocprofv3 --pmc
-    passes, calibrated on a copy of known size), or None when the summary is for another
-    workload or the kernel source has changed since the counters were taken."""
+    """HBM bytes per sweep launch from the committed counter summary of this workload (two
+    rocprofv3 --pmc passes, calibrated on a copy of known size), or None when there is
+    none or the kernel source has changed since the counters were taken."""
     import hashlib
-    if workload != "day_5min" or not os.path.exists(TRAFFIC_FILE):
+    path = traffic_file(workload)
+    if not os.path.exists(path):
         return None
     fields = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if not line.startswith("#") and ":" in line:
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
@@ -173,30 +183,82 @@ def roofline_of(inst, timing, traffic=None):
     }
 
 
-def cpu_baseline(inst, budget_s=12.0):
+def cpu_baseline(inst, budget_s=15.0):
+    """The FP64 oracle as it stands, on every host core, over the last n stages of the
+    workload (n chosen from a short probe so that the run takes about budget_s), and on
+    one thread over its last few stages.  Rates are feasible candidates per second; every
+    stage of a workload has the same candidate count."""
     import oracle
     cores = host_cores()
-    t0 = time.perf_counter()
-    n = 0
-    while True:
-        oracle.solve(inst.storage, inst.lam, inst.P, keep_all=False, want_policy=True,
-                     threads=cores)
-        n += 1
-        if time.perf_counter() - t0 >= budget_s:
-            break
-    dt = time.perf_counter() - t0
-    # the same oracle on one thread, over the last 24 stages of the workload (a bounded
-    # sample; every stage has the same candidate count)
-    T1 = min(24, inst.T)
-    lam1, P1 = inst.lam[-T1:], inst.P[-T1:]
-    t1 = time.perf_counter()
-    oracle.solve(inst.storage, lam1, P1, keep_all=False, want_policy=True, threads=1)
-    dt1 = time.perf_counter() - t1
-    return {"value": round(inst.candidates() * n / dt, 1), "unit": "updates/s", "cores": cores,
+    per_stage = inst.candidates() / inst.T
+
+    def run(n, threads):
+        t0 = time.perf_counter()
+        oracle.solve(inst.storage, inst.lam[-n:], inst.P[-n:], keep_all=False,
+                     want_policy=True, threads=threads)
+        return time.perf_counter() - t0
+
+    n0 = min(inst.T, 4)
+    dt0 = run(n0, cores)
+    n = int(max(n0, min(inst.T, budget_s / max(dt0 / n0, 1e-9))))
+    dt = run(n, cores)
+    n1 = min(inst.T, 4 if per_stage > 2e7 else 24)
+    dt1 = run(n1, 1)
+    return {"value": round(per_stage * n / dt, 1), "unit": "updates/s", "cores": cores,
             "kind": "oracle",
-            "sample": f"{n} full solve(s) of {inst.name} (FP64 C loops, OpenMP over k)",
-            "single_thread": {"value": round(inst.candidates() / inst.T * T1 / dt1, 1),
-                              "sample": f"the last {T1} stages of {inst.name}, 1 thread"}}
+            "sample": f"the last {n} of {inst.T} stages of {inst.name} ({dt:.1f} s; FP64 C "
+                      f"loops, OpenMP over price states, {cores} threads)",
+            "single_thread": {"value": round(per_stage * n1 / dt1, 1),
+                              "sample": f"the last {n1} stages of {inst.name}, 1 thread"}}
+
+
+def cpu_timings():
+    """CPU times of the other workloads: the oracle (FP64 C loops, all cores) on the hourly
+    day, the five-minute day and the adjoint of the five-minute day (the oracle's adjoint
+    under the oracle's own policies, after its solve), and Algorithm 1 as the paper runs it
+    (NumPy, materialised S x P x R payoff tensor, one price sample per price state) on the
+    hourly day (whole) and on the five-minute day shapes (a few stages)."""
+    import numpy as np
+    import oracle
+    from oracle import alg1
+    import workloads as wl
+    cores = host_cores()
+    out = {"cores": cores}
+    for inst in (wl.day_hourly_small(), wl.day_5min()):
+        t0 = time.perf_counter()
+        ref = oracle.solve(inst.storage, inst.lam, inst.P, keep_all=True, threads=cores)
+        dt = time.perf_counter() - t0
+        out[f"oracle_{inst.name}"] = {"s": round(dt, 3),
+                                      "updates_per_s": round(inst.candidates() / dt, 1)}
+        if inst.K == 100:
+            seed = wl.default_seed(inst.K, inst.storage.S).astype(np.float64)
+            t0 = time.perf_counter()
+            oracle.adjoint(inst.storage, inst.lam, inst.P, ref["V"], ref["policy"], seed,
+                           threads=cores)
+            da = time.perf_counter() - t0
+            out[f"oracle_adjoint_{inst.name}"] = {"s": round(da, 3),
+                                                  "adjoint_over_solve": round(da / dt, 3)}
+        del ref
+        # Algorithm 1 in NumPy on the same shapes: the integer-step action grid of the
+        # window, R = K price samples (the stage's levels) with equal probabilities
+        st = inst.storage
+        s_hat = np.arange(st.S) * float(st.delta)
+        p_hat = np.array([-(k * float(st.delta) / float(st.eta_c)) for k in range(st.w_up, 0, -1)]
+                         + [0.0] + [k * float(st.delta) * float(st.eta_d)
+                                    for k in range(1, st.w_down + 1)])
+        nT = inst.T if inst.K <= 10 else 3
+        pi = np.full(inst.K, 1.0 / inst.K)
+        pre = alg1.precompute(s_hat, p_hat, float(st.eta_c))
+        V = np.zeros(st.S)
+        t0 = time.perf_counter()
+        for t in range(inst.T, inst.T - nT, -1):
+            V, _ = alg1.stage(pre, p_hat, inst.lam[t - 1], pi, V)
+        dt = time.perf_counter() - t0
+        out[f"algorithm1_numpy_{inst.name}"] = {
+            "stages": nT, "s": round(dt, 3),
+            "sample_action_pairs_per_s": round(st.S * p_hat.size * inst.K * nT / dt, 1),
+            "threads": "NumPy (single-threaded element-wise ops)"}
+    return out
 
 
 def adjoint_ratio(dp, torch, inst, reps=5):
@@ -312,10 +374,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="day_5min")
+    ap.add_argument("--workload", default="year_hourly")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
-    ap.add_argument("--extra", default="year,adjoint,batch,table3",
+    ap.add_argument("--extra", default="day,adjoint,batch,table3,cpu",
                     help="comma-separated extras to run after the headline line's steps")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the steps, copy 256 MiB device-to-device once (a kernel of known "
@@ -365,19 +427,23 @@ def main():
     wanted = set() if args.no_extra else {x for x in args.extra.split(",") if x}
     if wanted:
         extra = {}
-        if "year" in wanted:
-            year = wl.year_hourly()
-            ysec, ytim = timed_solves(dp, torch, year, 2, 1)
-            extra["year_hourly"] = {"workload": year.name, "ms": round(ysec * 1e3, 2),
-                                    "updates_per_s": round(year.candidates() / ysec, 1),
-                                    "roofline": roofline_of(year, ytim)}
-            del year
+        for key, make in (("day", wl.day_5min), ("year", wl.year_hourly)):
+            if key in wanted and make.__name__ != args.workload:
+                other = make()
+                osec, otim = timed_solves(dp, torch, other, 5 if other.T < 1000 else 2, 1)
+                extra[make.__name__] = {"workload": other.name, "ms": round(osec * 1e3, 3),
+                                        "updates_per_s": round(other.candidates() / osec, 1),
+                                        "roofline": roofline_of(other, otim,
+                                                                measured_traffic(make.__name__))}
+                del other
         if "adjoint" in wanted:
             extra["adjoint_vs_value"] = adjoint_ratio(dp, torch, wl.day_5min_adjoint())
         if "batch" in wanted:
             extra["batched_vs_looped"] = batch_compare(dp, torch)
         if "table3" in wanted:
             extra["table3_independent"] = table3_independent(dp, torch)
+        if "cpu" in wanted:
+            extra["cpu_timings"] = cpu_timings()
         line["extra"] = extra
     print(json.dumps(line), flush=True)
 

@@ -30,17 +30,22 @@ def test_roofline_arithmetic():
 
 
 def test_traffic_summary_matches_kernel_source():
-    # the committed counter summary is for the current sweep source, else it must read None
+    # a committed counter summary counts only while it is for the current sweep source
     import hashlib
     digest = hashlib.sha256(open(bench.KERNEL_SOURCE, "rb").read()).hexdigest()
-    fields = dict(line.split(":", 1) for line in open(bench.TRAFFIC_FILE)
-                  if not line.startswith("#") and ":" in line)
-    t = bench.measured_traffic("day_5min")
-    if fields["kernel_source_sha256"].strip() == digest:
-        assert t == int(fields["bytes_per_launch"])
-    else:
-        assert t is None
-    assert bench.measured_traffic("year_hourly") is None
+    for workload in ("year_hourly", "day_5min"):
+        path = bench.traffic_file(workload)
+        t = bench.measured_traffic(workload)
+        if not os.path.exists(path):
+            assert t is None
+            continue
+        fields = dict(line.split(":", 1) for line in open(path)
+                      if not line.startswith("#") and ":" in line)
+        if fields["kernel_source_sha256"].strip() == digest:
+            assert t == int(fields["bytes_per_launch"])
+        else:
+            assert t is None
+    assert bench.measured_traffic("no_such_workload") is None
 
 
 def test_more_than_one_gpu_is_refused():
