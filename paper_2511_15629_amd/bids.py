@@ -17,6 +17,17 @@ For every price lam, max_p lam p + U~(p) = max_p lam p + U(p): the envelope chan
 quantities are offered, never the optimal profit.  The quantity cleared at lam is the hull
 vertex maximising lam p + U~(p) (the largest such quantity on a tie, the supply-curve
 convention).
+
+Markov prices.  The bid for stage t is decided at t - 1, before the price state k of stage
+t is known (Sec. II-C), but here the continuation W_t[k] depends on k, which the price
+itself reveals: the curve of state k applies when the price is lam_t[k].  Each state's
+curve gives the quantity q_k it clears at its own level lam_t[k]; the bid submitted for
+(t, s) is the price-sorted monotone envelope of the points (lam_t[k], q_k): at the level
+of state k it offers max{q_k' : lam_t[k'] <= lam_t[k]}, the least non-decreasing supply
+schedule that offers at least q_k at every level (market rules require a non-decreasing
+curve).  Where the q_k are already non-decreasing in price (always so with independent
+prices, where every state has the same concave U~) the envelope offers exactly q_k and
+clears the DP's value; elsewhere it gives up the difference, which `MarkovBid` reports.
 """
 from __future__ import annotations
 
@@ -104,3 +115,67 @@ def stage_bids(V_next: np.ndarray, P_t: np.ndarray, s: int, storage) -> List[Bid
     depend on k; with independent prices all K curves coincide)."""
     K = np.asarray(P_t).shape[0]
     return [bid_curve(expectation_row(V_next, P_t, k), s, storage) for k in range(K)]
+
+
+def monotone_envelope(levels: np.ndarray, q: np.ndarray) -> np.ndarray:
+    """Least non-decreasing majorant of the points (levels[k], q[k]) in price order:
+    out[k] = max{q[k'] : levels[k'] <= levels[k]} (equal levels share their maximum)."""
+    levels = np.asarray(levels, dtype=np.float64)
+    q = np.asarray(q, dtype=np.float64)
+    order = np.argsort(levels, kind="stable")
+    run = np.maximum.accumulate(q[order])
+    out = np.empty_like(q)
+    out[order] = run
+    # states at one price level offer the largest quantity of the group
+    lv = levels[order]
+    i = 0
+    while i < lv.size:
+        e = i
+        while e + 1 < lv.size and lv[e + 1] == lv[i]:
+            e += 1
+        out[order[i:e + 1]] = run[e]
+        i = e + 1
+    return out
+
+
+@dataclasses.dataclass
+class MarkovBid:
+    """The bid for one stage and incoming SoC under a Markov price chain."""
+    levels: np.ndarray   # lam_t[k]
+    q: np.ndarray        # quantity each state's own curve clears at its level
+    j: np.ndarray        # next state of that quantity (the DP policy where unique)
+    q_bid: np.ndarray    # monotone envelope: quantity offered at each level
+    j_bid: np.ndarray    # next state reached when the bid clears at level k
+    profit: np.ndarray   # realised lam_t[k] q_bid + U_k(q_bid) at each level
+    value: np.ndarray    # max_p lam_t[k] p + U_k(p) (the DP value V_t[k][s])
+
+    @property
+    def monotone_already(self) -> bool:
+        return bool(np.array_equal(self.q, self.q_bid))
+
+    def schedule(self):
+        """(price, quantity) steps of the submitted curve, ascending in price."""
+        o = np.argsort(self.levels, kind="stable")
+        return [(float(self.levels[k]), float(self.q_bid[k])) for k in o]
+
+
+def markov_bid(V_next: np.ndarray, P_t: np.ndarray, lam_t: np.ndarray, s: int, storage) -> MarkovBid:
+    """Per-state curves (Eq. (7)-(10)) cleared at their own levels, combined into one
+    monotone bid by the price-sorted envelope."""
+    lam_t = np.asarray(lam_t, dtype=np.float64)
+    curves = stage_bids(V_next, P_t, s, storage)
+    K = len(curves)
+    q = np.empty(K)
+    jq = np.empty(K, dtype=np.int64)
+    value = np.empty(K)
+    for k, bc in enumerate(curves):
+        q[k], jq[k], value[k] = bc.clear(float(lam_t[k]))
+    q_bid = monotone_envelope(lam_t, q)
+    j_bid = np.empty(K, dtype=np.int64)
+    profit = np.empty(K)
+    for k, bc in enumerate(curves):
+        i = int(np.flatnonzero(bc.p == q_bid[k])[0])   # every curve has the same quantity grid
+        j_bid[k] = bc.j[i]
+        profit[k] = lam_t[k] * bc.p[i] + bc.U[i]
+    return MarkovBid(levels=lam_t, q=q, j=jq, q_bid=q_bid, j_bid=j_bid, profit=profit,
+                     value=value)

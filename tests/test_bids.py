@@ -68,3 +68,63 @@ def test_start_cost_makes_the_envelope_bridge_the_idle_point():
     assert 10 in bc.j[bc.hull]
     segs = bc.segments()
     assert any(a < 0.0 < b or b == 0.0 or a == 0.0 for a, b, _ in segs)
+
+
+def test_monotone_envelope_is_the_least_nondecreasing_majorant():
+    # Definition pin by enumeration: among all non-decreasing integer schedules on 0..4 that
+    # lie on or above q at every level (in price order), the pointwise minimum is the one
+    # returned (ties in price share one offer).
+    import itertools
+    rng = np.random.default_rng(9)
+    for _ in range(40):
+        K = int(rng.integers(1, 6))
+        levels = rng.choice([-5.0, 0.0, 3.0, 7.5, 20.0], size=K)
+        q = rng.integers(0, 5, size=K).astype(np.float64)
+        o = np.argsort(levels, kind="stable")
+        best = None
+        for cand in itertools.product(range(5), repeat=K):
+            c = np.array(cand, dtype=np.float64)
+            ok = np.all(c >= q)
+            ok &= all(c[o[i]] <= c[o[i + 1]] for i in range(K - 1))
+            ok &= all(c[a] == c[b] for a in range(K) for b in range(K) if levels[a] == levels[b])
+            if ok:
+                best = c if best is None else np.minimum(best, c)
+        np.testing.assert_array_equal(bids.monotone_envelope(levels, q), best)
+
+
+def test_independent_prices_bid_is_monotone_and_clears_the_dp_value():
+    # With every row of P_t equal (stagewise independence, the paper's setting) all states
+    # share one concave U~, so the per-state quantities are already non-decreasing in price
+    # and the combined bid clears exactly the DP value at every level.
+    rng = np.random.default_rng(11)
+    T, K, S = 6, 5, 30
+    lam = wl.f32(rng.uniform(-40, 90, size=(T, K)))
+    rows = wl.quantize_rows(rng.dirichlet(np.ones(K), size=T))
+    P = np.repeat(rows[:, None, :], K, axis=1)
+    st = wl.Storage(S=S, w_up=6, w_down=7, delta=0.25, eta_c=0.9, eta_d=0.9, c_deg=1.0).as_f32()
+    out = oracle.solve(st, lam, P)
+    for t in range(1, T + 1):
+        for s in range(S):
+            mb = bids.markov_bid(out["V"][t], P[t - 1], lam[t - 1], s, st)
+            assert mb.monotone_already
+            np.testing.assert_allclose(mb.profit, out["V"][t - 1][:, s], rtol=0, atol=1e-9)
+
+
+@pytest.mark.parametrize("seed,c_start", [(6, 0.0), (7, 3.0)])
+def test_markov_bid_is_monotone_and_never_beats_the_dp(seed, c_start):
+    inst = wl.random_small(seed, 6, 6, 30, 6, 7, c_start=c_start, lam_lo=-80.0)
+    out = oracle.solve(inst.storage, inst.lam, inst.P)
+    n_mono = 0
+    for t in range(1, inst.T + 1):
+        for s in range(inst.storage.S):
+            mb = bids.markov_bid(out["V"][t], inst.P[t - 1], inst.lam[t - 1], s, inst.storage)
+            sched = mb.schedule()
+            assert all(b[1] >= a[1] for a, b in zip(sched, sched[1:]))
+            assert np.all(mb.q_bid >= mb.q)
+            np.testing.assert_allclose(mb.value, out["V"][t - 1][:, s], rtol=0, atol=1e-9)
+            assert np.all(mb.profit <= mb.value + 1e-9)
+            if mb.monotone_already:
+                n_mono += 1
+                np.testing.assert_allclose(mb.profit, mb.value, rtol=0, atol=1e-9)
+    print(f"per-state quantities already monotone in price at {n_mono} of "
+          f"{inst.T * inst.storage.S} (t, s)")
