@@ -14,7 +14,8 @@ carries:
   roofline      the Bellman-sweep kernel (dominant): feasible candidates per launch over
                 its average launch time, measured with HIP events on the solve's stream
                 in a second pass of the same steps right after the timed ones, against
-                the VALU issue bound (1.5 lane-instructions per candidate);
+                the FP32 vector bound (an add and a max per candidate at 32 lanes per
+                clock per SIMD);
   cpu_baseline  the FP64 oracle timed on this host's cores on a bounded sample of the
                 same workload (its last stages);
   extra         the five-minute day solve, the adjoint/value time ratio and the
@@ -31,10 +32,13 @@ import sys
 import threading
 import time
 
-# Peak of the sweep: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 3.93e13 VALU lane-instructions/s;
-# one candidate needs at least one v_add_f32 and half a v_max3_f32 (1.5 instructions).
-VALU_LANE_OPS = 256 * 64 * 2.4e9
-SWEEP_PEAK_GUPD = VALU_LANE_OPS / 1.5 / 1e9
+# Peak of the sweep: the FP32 vector rate, 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz = 7.86e13
+# lane-operations/s (the published 157.3 TFLOP/s counts an FMA as two), with one candidate
+# costing one add and one max (two operations; two-input add and fma issue at 2 clocks per
+# wave64 instruction, v_max3_f32 at 4, so a pair of candidates costs 2 adds + 1 max3 = 8
+# clocks either way): 3.93e13 candidates/s.
+VALU_LANE_OPS = 256 * 4 * 32 * 2.4e9
+SWEEP_PEAK_GUPD = VALU_LANE_OPS / 2.0 / 1e9
 # Dense FP32 matrix-core peak of the MI355X (published): 157.3 TFLOP/s.
 MFMA_F32_PEAK_TFLOPS = 157.3
 

@@ -271,7 +271,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
     // stage's normalisation constant W_t[0][0] and the offset C_{t+1} (for the epilogue).
     const float *Wk = a.W + (size_t)k * a.ldw;
     float lam = 0.0f, shift = 0.0f;
-    double off_next = 0.0, rsum = 1.0;
+    double off_next = 0.0, rsum_m1 = 0.0;
     for (int i4 = 0; i4 < nwl; i4 += 4 * NW * 64) {     // nwl > 0: at least one pass
         float w[4];
 #pragma unroll
@@ -285,7 +285,8 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
             lam = a.lam[k];
             shift = a.W[0];
             off_next = a.off_next[0];
-            if (a.P) rsum = row_sum_f64(a.P + (size_t)k * a.K, a.K, tid & 63);
+            if (a.rho1) rsum_m1 = a.rho1[k];
+            else if (a.P) rsum_m1 = row_sum_f64(a.P + (size_t)k * a.K, a.K, tid & 63) - 1.0;
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -353,7 +354,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
     // W_t was formed from the normalised V_{t+1}; its true value adds rho_k C_{t+1}, of which
     // C_{t+1} is carried by the offset and (rho_k - 1) C_{t+1} goes into the row (exactly 0,
     // and skipped, when the row sums to 1)
-    const double corr = (rsum - 1.0) * off_next;
+    const double corr = rsum_m1 * off_next;
     for (int o = tid; o < TS; o += NW * 64) {
         const int s = s0 + o;
         if (s >= S) break;
@@ -452,6 +453,243 @@ hipError_t launch_sweep(const SweepArgs &a, const SweepShape &sh, hipStream_t st
     DP_SWEEP_SHAPES(X)
 #undef X
     return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------------------------------
+// Balanced Bellman sweep (the default for the single solve).
+//
+// The SoC indices of a row (price state k) are cut into groups of R consecutive outputs.
+// Group g has its own move range (flat_group: from the smallest feasible move of its last
+// output, rounded down to a multiple of 4, to the largest of its first output) cut into
+// n_g chunks of D moves; a work unit is (group, chunk), R x D candidates.  Block (p, k)
+// takes the groups [g0, g1) of part p of row k (the host cuts each row into beta parts of
+// about equal work).  Each of its groups gets L lanes (the part's lane budget), lane
+// slot-major: lane t takes group t mod ngr and run slot t / ngr, so neighbouring lanes
+// read W R floats apart and the same reward entries.  A group's chunks are cut into L
+// contiguous runs differing by at most one chunk, the longer runs in the first slots, so
+// that most waves hold runs of one length (a wave runs as long as its longest lane).
+//
+// A lane keeps, per output, the running maximum of its chunks and the first chunk that
+// raised it (strict >, so equal later maxima keep the earlier chunk).  The lanes of a group
+// combine through a 64-bit LDS atomic max on (order-preserving bits of the value, inverted
+// chunk index): the largest value, and among equal values the smallest chunk.  The
+// winning chunk is then scanned once more for the first move whose recomputed candidate
+// equals the maximum bit for bit, which is the smallest next state attaining it.  The
+// maximum is exact and the candidates are formed from the same operands as in every other
+// sweep kernel, so values and policies are bitwise those of sweep_kernel.
+// ------------------------------------------------------------------------------------
+// Order-preserving map of a float to 32 bits (larger value -> larger key); -0 maps as +0.
+__device__ __forceinline__ unsigned flat_key(float v)
+{
+    const unsigned u = __float_as_uint(v + 0.0f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float flat_unkey(unsigned k)
+{
+    return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
+}
+
+template <int R, int D, int NT>
+__global__ __launch_bounds__(NT) void sweep_flat_kernel(SweepArgs a, FlatArgs f)
+{
+    extern __shared__ float4 smem4[];
+    float *smem = reinterpret_cast<float *>(smem4);
+    constexpr int NWV = NT / 64;
+    const int p = blockIdx.x, k = blockIdx.y, tid = threadIdx.x;
+    const int S = a.S, w_up = a.w_up, w_down = a.w_down;
+    const int g0 = f.part[p].g0, g1 = f.part[p].g1, Lg = f.part[p].L;
+    const FlatLayout L = flat_layout(R, D, g0, g1, S, w_up, w_down);
+    const int ngr = L.ngr;
+    float *Wl = smem;
+    float *rl = Wl + L.nW;
+    unsigned long long *acc = reinterpret_cast<unsigned long long *>(rl + L.nRw);
+
+    const float NEG = -INFINITY;
+    // The W segment first (four loads per thread in flight), then the scalars: the block
+    // waits for one memory round trip.
+    const float *Wk = a.W + (size_t)k * a.ldw;
+    float lam = 0.0f, shift = 0.0f;
+    double off_next = 0.0, rsum_m1 = 0.0;
+    for (int i4 = 0; i4 < L.nW; i4 += 4 * NT) {
+        float w[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = i4 + u * NT + tid;
+            const int j = L.j_org + i;
+            w[u] = (i < L.nW && j >= 0 && j < S) ? Wk[j] : NEG;
+        }
+        if (i4 == 0) {
+            __builtin_amdgcn_sched_barrier(0);
+            lam = a.lam[k];
+            shift = a.W[0];
+            off_next = a.off_next[0];
+            if (a.rho1) rsum_m1 = a.rho1[k];
+            else if (a.P) rsum_m1 = row_sum_f64(a.P + (size_t)k * a.K, a.K, tid & 63) - 1.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = i4 + u * NT + tid;
+            if (i < L.nW) Wl[i] = w[u];
+        }
+    }
+    for (int i = tid; i < L.nRw; i += NT) {
+        const int d = L.r_org + i;
+        rl[i] = (d >= -w_down && d <= w_up) ? move_reward(lam, d, a.pay) : NEG;
+    }
+    for (int i = tid; i < ngr * R; i += NT) acc[i] = 0ull;
+
+    // This lane's group and run of chunks: slot-major order, so consecutive lanes take
+    // consecutive groups at the same run slot (their W reads are R floats apart, their
+    // reward reads coincide).  Group g's n chunks are cut into Lg runs, the n mod Lg longer
+    // ones (ceil(n / Lg) chunks) in the first slots.
+    const int gl = tid % ngr, slot = tid / ngr;
+    int c_begin = 0, cnt = 0, dlo4 = 0;
+    if (slot < Lg) {
+        int n;
+        flat_group(g0 + gl, R, D, S, w_up, w_down, dlo4, n);
+        const int c_lo = n / Lg, rem = n - c_lo * Lg;
+        cnt = c_lo + (slot < rem ? 1 : 0);
+        c_begin = slot * c_lo + min(slot, rem);
+    }
+    __syncthreads();
+
+    float best[R];
+    int cid[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        best[i] = NEG;
+        cid[i] = 0;
+    }
+    if (cnt > 0) {
+        const float *wsrc = Wl + (R * (g0 + gl) + dlo4 - L.j_org);
+        const float *rsrc0 = rl + (dlo4 - L.r_org);
+        for (int c = c_begin; c < c_begin + cnt; ++c) {
+            float w[R + D];
+            const float4 *src = reinterpret_cast<const float4 *>(wsrc + c * D);
+#pragma unroll
+            for (int m = 0; m < (R + D) / 4; ++m) {
+                const float4 v = src[m];
+                w[4 * m + 0] = v.x;
+                w[4 * m + 1] = v.y;
+                w[4 * m + 2] = v.z;
+                w[4 * m + 3] = v.w;
+            }
+            float r[D];
+            const float4 *rsrc = reinterpret_cast<const float4 *>(rsrc0 + c * D);
+#pragma unroll
+            for (int m = 0; m < D / 4; ++m) {
+                const float4 v = rsrc[m];
+                r[4 * m + 0] = v.x;
+                r[4 * m + 1] = v.y;
+                r[4 * m + 2] = v.z;
+                r[4 * m + 3] = v.w;
+            }
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                float m = best[i];
+#pragma unroll
+                for (int d = 0; d < D; ++d) m = fmaxf(m, w[i + d] + r[d]);
+                cid[i] = (m > best[i]) ? c : cid[i];
+                best[i] = m;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            if (best[i] > NEG) {
+                const unsigned long long key =
+                    ((unsigned long long)flat_key(best[i]) << 32) | (0xffffffffu - (unsigned)cid[i]);
+                atomicMax(&acc[gl * R + i], key);
+            }
+        }
+    }
+    __syncthreads();
+
+    const double Ct = off_next + (double)shift;
+    const double corr = rsum_m1 * off_next;
+    for (int o = tid; o < ngr * R; o += NT) {
+        const int gi = o / R, i = o - gi * R;
+        const int s = R * (g0 + gi) + i;
+        if (s >= S) continue;
+        const unsigned long long key = acc[o];
+        const float bv = flat_unkey((unsigned)(key >> 32));
+        const int bc = (int)(0xffffffffu - (unsigned)(key & 0xffffffffull));
+        int dlo4, n;
+        flat_group(g0 + gi, R, D, S, w_up, w_down, dlo4, n);
+        const float *wq = Wl + (R * (g0 + gi) + i + dlo4 + bc * D - L.j_org);
+        const float *rq = rl + (dlo4 + bc * D - L.r_org);
+        int arg = 0;
+#pragma unroll
+        for (int d = D - 1; d >= 0; --d) {
+            const float x = wq[d] + rq[d];
+            if (x == bv) arg = d;
+        }
+        const int j = s + dlo4 + bc * D + arg;
+        const float vn = corr == 0.0 ? bv - shift : (float)((double)(bv - shift) + corr);
+        const size_t idx = (size_t)k * S + s;
+        a.vnorm[(size_t)k * a.ldv + s] = vn;
+        if (a.vabs) __builtin_nontemporal_store((float)((double)vn + Ct), &a.vabs[idx]);
+        if (a.pol) __builtin_nontemporal_store((int16_t)j, &a.pol[idx]);
+        if (a.ckpt_v) __builtin_nontemporal_store(vn, &a.ckpt_v[idx]);
+    }
+    if (k == 0 && p == 0 && tid == 0) {
+        a.off_cur[0] = Ct;
+        if (a.ckpt_off) a.ckpt_off[0] = Ct;
+    }
+}
+
+#define DP_FLAT_SHAPES(X) \
+    X(8, 16, 512)         \
+    X(8, 16, 256)         \
+    X(4, 16, 512)         \
+    X(4, 16, 256)         \
+    X(8, 8, 512)          \
+    X(4, 8, 256)
+
+bool flat_shape_supported(const FlatShape &sh)
+{
+#define X(r, d, nt) \
+    if (sh.R == r && sh.D == d && sh.NT == nt) return true;
+    DP_FLAT_SHAPES(X)
+#undef X
+    return false;
+}
+
+size_t flat_lds_bytes(const FlatShape &sh, const FlatLayout &L)
+{
+    return sizeof(float) * ((size_t)L.nW + L.nRw) + sizeof(unsigned long long) * (size_t)L.ngr * sh.R;
+}
+
+hipError_t launch_sweep_flat(const SweepArgs &a, const FlatShape &sh, const FlatArgs &f,
+                             size_t lds, hipStream_t stream)
+{
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    const dim3 grid(f.beta, a.K);
+#define X(r, d, nt)                                                                     \
+    if (sh.R == r && sh.D == d && sh.NT == nt) {                                        \
+        hipLaunchKernelGGL((sweep_flat_kernel<r, d, nt>), grid, dim3(nt), lds, stream, a, f); \
+        return hipGetLastError();                                                       \
+    }
+    DP_FLAT_SHAPES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+// rho1[t][k] = row_sum_f64(P_t[k]) - 1: one wave per row, the sweep's summation order.
+__global__ __launch_bounds__(256) void row_sums_kernel(const float *__restrict__ P, int K,
+                                                       int rows, double *__restrict__ rho1)
+{
+    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= rows) return;                      // per wave: every lane of it leaves together
+    const double s = row_sum_f64(P + (size_t)r * K, K, threadIdx.x & 63);
+    if ((threadIdx.x & 63) == 0) rho1[r] = s - 1.0;
+}
+
+hipError_t launch_row_sums(const float *P, int K, int nstage, double *rho1, hipStream_t stream)
+{
+    const int rows = K * nstage;
+    hipLaunchKernelGGL(row_sums_kernel, dim3((rows + 3) / 4), dim3(256), 0, stream, P, K, rows,
+                       rho1);
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------------------------------
@@ -792,6 +1030,7 @@ __global__ __launch_bounds__(NW * 64 * tiles_per_block<NW>()) void batched_sweep
     a.ldw = d.ld;
     a.lam = d.lam + (size_t)(t - 1) * d.K;
     a.P = d.P ? d.P + (size_t)(t - 1) * d.K * d.K : nullptr;
+    a.rho1 = nullptr;
     a.K = d.K;
     a.S = d.S;
     a.w_up = d.w_up;

@@ -21,7 +21,10 @@ def test_roofline_arithmetic():
     assert r["avg_launch_us"] == pytest.approx(2.0)
     assert r["achieved"] == pytest.approx(per_launch / 2.0e-6 / 1e9, rel=1e-3)
     assert r["frac"] == pytest.approx(r["achieved"] / r["peak"], rel=1e-3, abs=1e-4)
-    assert r["peak"] == pytest.approx(256 * 64 * 2.4e9 / 1.5 / 1e9, rel=1e-6)
+    # an add and a max per candidate on 256 CUs x 4 SIMDs x 32 FP32 lanes at 2.4 GHz, which
+    # is the published FP32 vector peak (157.3 TFLOP/s) at two operations per candidate
+    assert r["peak"] == pytest.approx(256 * 4 * 32 * 2.4e9 / 2 / 1e9, rel=1e-6)
+    assert r["peak"] == pytest.approx(157.3e12 / 2 / 2 / 1e9, rel=1e-3)
     assert r["traffic"] == 12345
     e = r["expectation"]
     flop = 2.0 * inst.K ** 2 * inst.storage.S
