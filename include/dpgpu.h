@@ -154,6 +154,21 @@ size_t dp_ckpt_bytes(const dp_problem *pb);
 int dp_solve(const dp_problem *pb, const float *lam, const float *P, const float *v_term,
              float *V, int16_t *policy, void *ckpt, void *ws, size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc): dp_solve without the workspace argument.  The
+ * solver state lives in a device array inside the library, DP_NOALLOC_SCRATCH_BYTES per GPU,
+ * held from the library's first use on that GPU until the process ends; the call allocates
+ * nothing.  Arguments and results as dp_solve (bitwise the same values and policies).
+ * Every call on a GPU shares that GPU's array: calls that overlap on one GPU (concurrent
+ * streams, threads, processes sharing a device context) race and must be ordered by the
+ * caller; the array needs no clearing between calls.
+ * Errors: as dp_solve, plus DP_ENOTSUP when the problem's solver state exceeds the array
+ * (about 3 K S_pad 4 bytes + 8 (T + 2) bytes + repacked rows of P; S_pad = S rounded up to
+ * 64), and DP_EINVAL with DP_VALIDATE (validation reads a flag back to the host). */
+#define DP_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+int dp_solve_noalloc(const dp_problem *pb, const float *lam, const float *P,
+                     const float *v_term, float *V, int16_t *policy, void *ckpt, void *stream);
+
 /* Bytes of device workspace dp_adjoint needs. */
 size_t dp_adjoint_workspace_bytes(const dp_problem *pb);
 

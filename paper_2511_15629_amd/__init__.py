@@ -17,7 +17,8 @@ import torch
 from . import _lib
 from ._lib import DPError, DP_STORE_V_ALL, DP_VALIDATE, check, lib, make_problem
 
-__all__ = ["solve", "adjoint", "Solver", "DPFunction", "DPError", "set_sweep_shape", "sweep_plan",
+__all__ = ["solve", "solve_noalloc", "adjoint", "Solver", "DPFunction", "DPError",
+           "set_sweep_shape", "sweep_plan",
            "BatchPlan", "kernel_timing", "solve_independent", "power_grid_size"]
 
 
@@ -140,6 +141,32 @@ class Solver:
                              _ptr(self.V), _ptr(self.policy), _ptr(self.ckpt), _ptr(self.ws),
                              ctypes.c_size_t(self.ws.numel()), _stream(stream)))
         return self.V
+
+
+def solve_noalloc(lam: torch.Tensor, P: torch.Tensor, storage, V: torch.Tensor,
+                  policy: Optional[torch.Tensor] = None, v_term: Optional[torch.Tensor] = None,
+                  *, store_all: bool = False, ckpt: Optional[torch.Tensor] = None,
+                  ckpt_every: int = 0, stream=None) -> torch.Tensor:
+    """dp_solve_noalloc: the solve into caller-given outputs (V [T+1, K, S] with store_all,
+    else [K, S]; policy [T, K, S] int16 or None), with the solver state in the library's own
+    device array, so the call allocates nothing (argument checks only, no copies)."""
+    T, K = lam.shape
+    S = int(storage.S)
+    _check(lam, "lam", (T, K), torch.float32, lam.device)
+    _check(P, "P", (T, K, K), torch.float32, lam.device)
+    _check(V, "V", (T + 1, K, S) if store_all else (K, S), torch.float32, lam.device)
+    if policy is not None:
+        _check(policy, "policy", (T, K, S), torch.int16, lam.device)
+    if v_term is not None:
+        _check(v_term, "v_term", (K, S), torch.float32, lam.device)
+    pb = make_problem(T, K, storage, DP_STORE_V_ALL if store_all else 0, ckpt_every)
+    if ckpt is not None:
+        _check(ckpt, "ckpt", None, torch.uint8, lam.device)
+        if ckpt.numel() < lib().dp_ckpt_bytes(ctypes.byref(pb)):
+            raise ValueError("ckpt buffer smaller than dp_ckpt_bytes")
+    check(lib().dp_solve_noalloc(ctypes.byref(pb), _ptr(lam), _ptr(P), _ptr(v_term), _ptr(V),
+                                 _ptr(policy), _ptr(ckpt), _stream(stream)))
+    return V
 
 
 def _iid_problem(T, R, S, delta, eta, p_bar, store_all=False):

@@ -27,7 +27,7 @@ DP_VALIDATE = 0x2
 # Every symbol include/dpgpu.h declares (the tests check the library exports all of them).
 EXPORTS = (
     "dp_abi_version", "dp_strerror", "dp_last_error", "dp_workspace_bytes", "dp_ckpt_bytes",
-    "dp_solve", "dp_adjoint_workspace_bytes", "dp_adjoint", "dp_batch_plan_create",
+    "dp_solve", "dp_solve_noalloc", "dp_adjoint_workspace_bytes", "dp_adjoint", "dp_batch_plan_create",
     "dp_batch_solve", "dp_batch_solve_eager", "dp_batch_solve_looped", "dp_batch_plan_describe",
     "dp_batch_plan_destroy", "dp_set_sweep_shape", "dp_sweep_plan", "dp_set_timing",
     "dp_get_timing",
@@ -80,6 +80,7 @@ def lib():
             "dp_workspace_bytes": ([PP], sz),
             "dp_ckpt_bytes": ([PP], sz),
             "dp_solve": ([PP, p, p, p, p, p, p, p, sz, p], i),
+            "dp_solve_noalloc": ([PP, p, p, p, p, p, p, p], i),
             "dp_adjoint_workspace_bytes": ([PP], sz),
             "dp_adjoint": ([PP, p, p, p, p, p, p, p, p, p, p, p, sz, p], i),
             "dp_batch_plan_create": ([ctypes.POINTER(p), i, PP, ctypes.c_char_p, p], i),

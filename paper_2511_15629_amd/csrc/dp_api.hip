@@ -255,6 +255,20 @@ SweepChoice choose_sweep(const dp_problem *pb)
     return c;
 }
 
+SolveLayout solve_layout(const dp_problem *pb, size_t cap)
+{
+    SolveLayout L = solve_layout(pb);
+    // a smaller ring of repacked P_t only launches the repacking more often
+    while (L.total > cap && L.npk > 1) {
+        const int npk = L.npk >> 1;
+        L.Pp = L.flag + 256;
+        L.rho = L.Pp + align256((size_t)npk * sizeof(float) * dpk::packed_P_floats(pb->K));
+        L.total = L.rho + align256(sizeof(double) * (size_t)npk * pb->K);
+        L.npk = npk;
+    }
+    return L;
+}
+
 SolveLayout solve_layout(const dp_problem *pb)
 {
     SolveLayout L;
@@ -296,10 +310,13 @@ size_t ckpt_bytes(const dp_problem *pb)
 // out.vall slice t - t_lo (or out.v1 for t = t_lo), policies to out.pol slice t - t_lo.
 int run_stages(const dp_problem *pb, int t_lo, int t_hi, const float *lam, const float *P,
                const float *v_src, const double *off_src, const StageOutputs &out, void *ws,
-               hipStream_t stream)
+               hipStream_t stream, size_t ws_cap, bool timing)
 {
     const int K = pb->K, S = pb->st.S;
-    const SolveLayout L = solve_layout(pb);
+    const SolveLayout L = solve_layout(pb, ws_cap);
+    auto timer_mark = [timing](hipStream_t st, int kind, bool start) {
+        return timing ? ::timer_mark(st, kind, start) : hipSuccess;
+    };
     char *base = static_cast<char *>(ws);
     float *vbuf[2] = {reinterpret_cast<float *>(base + L.vA), reinterpret_cast<float *>(base + L.vB)};
     float *Wb = reinterpret_cast<float *>(base + L.W);
@@ -555,6 +572,34 @@ int dp_solve(const dp_problem *pb, const float *lam, const float *P, const float
 }
 
 // ------------------------------------------------------------------------------------
+// Allocation-free solve: the solver state lives in a file-scope device array of this
+// translation unit.  Its address on each device comes from hipGetSymbolAddress, taken once
+// per device with that device current; only that address is ever handed to kernels or
+// copies.
+// ------------------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[DP_NOALLOC_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[64];
+
+static int scratch_for_current_device(void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= 64) return fail(DP_ENOTSUP, "device index %d beyond 63", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!ptr) return fail(DP_EHIP, "no device address for the solver scratch");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return DP_OK;
+}
+
+// ------------------------------------------------------------------------------------
 // Adjoint.
 // ------------------------------------------------------------------------------------
 struct AdjLayout {
@@ -642,6 +687,31 @@ struct AdjEvents {
         return e;
     }
 };
+
+int dp_solve_noalloc(const dp_problem *pb, const float *lam, const float *P,
+                     const float *v_term, float *V, int16_t *policy, void *ckpt, void *stream_)
+{
+    int rc = validate_problem(pb);
+    if (rc != DP_OK) return rc;
+    if (!lam || !P || !V) return fail(DP_EINVAL, "lam, P and V must be non-NULL");
+    if (ckpt && pb->ckpt_every < 1) return fail(DP_EINVAL, "ckpt given but ckpt_every < 1");
+    if (pb->flags & DP_VALIDATE)
+        return fail(DP_EINVAL, "DP_VALIDATE reads a flag back to the host; use dp_solve");
+    const SolveLayout L = solve_layout(pb, DP_NOALLOC_SCRATCH_BYTES);
+    if (L.total > DP_NOALLOC_SCRATCH_BYTES)
+        return fail(DP_ENOTSUP, "the solver state needs %zu bytes; dp_solve_noalloc holds %zu "
+                    "(use dp_solve with a workspace)", L.total, (size_t)DP_NOALLOC_SCRATCH_BYTES);
+    void *ws = nullptr;
+    if ((rc = scratch_for_current_device(&ws)) != DP_OK) return rc;
+    StageOutputs out = {};
+    if (pb->flags & DP_STORE_V_ALL) out.vall = V;
+    else out.v1 = V;
+    out.pol = policy;
+    out.ckpt_every = pb->ckpt_every;
+    if (ckpt) ckpt_pointers(pb, ckpt, &out.ckpt_v, &out.ckpt_off);
+    return run_stages(pb, 1, pb->T, lam, P, v_term, nullptr, out, ws,
+                      static_cast<hipStream_t>(stream_), DP_NOALLOC_SCRATCH_BYTES, false);
+}
 
 size_t dp_adjoint_workspace_bytes(const dp_problem *pb)
 {

@@ -34,6 +34,9 @@ struct SolveLayout {
     size_t vA, vB, W, off, flag, Pp, rho, total;
 };
 SolveLayout solve_layout(const dp_problem *pb);
+// The same layout with the ring of repacked P_t shrunk until the total fits cap bytes (if it
+// can); results do not depend on the ring's size.
+SolveLayout solve_layout(const dp_problem *pb, size_t cap);
 
 struct StageOutputs {
     float *vall;         // [(t_hi - t_lo + 2)][K][S] absolute values, slice t - t_lo (nullable)
@@ -44,8 +47,9 @@ struct StageOutputs {
     int ckpt_every;
 };
 
+// ws holds solve_layout(pb, ws_cap); timing = false keeps the measurement hook's events out.
 int run_stages(const dp_problem *pb, int t_lo, int t_hi, const float *lam, const float *P,
                const float *v_src, const double *off_src, const StageOutputs &out, void *ws,
-               hipStream_t stream);
+               hipStream_t stream, size_t ws_cap = SIZE_MAX, bool timing = true);
 
 }  // namespace dpgpu
