@@ -170,6 +170,15 @@ def roofline_of(inst, timing, traffic=None):
     per_launch = inst.candidates() / inst.T            # candidates per sweep launch (avg)
     avg_s = sweep_ms / 1e3 / max(n_sweep, 1)
     achieved = per_launch / avg_s / 1e9
+    if n_exp == 0:
+        # one launch per stage: the expectation is formed inside the sweep launch
+        return {
+            "bound": "alu", "achieved": round(achieved, 1), "peak": round(SWEEP_PEAK_GUPD, 1),
+            "unit": "Gupd/s", "frac": round(achieved / SWEEP_PEAK_GUPD, 4), "traffic": traffic,
+            "traffic_GBps": None if traffic is None else round(traffic / avg_s / 1e9, 1),
+            "kernel": "sweep_kernel (expectation fused)", "avg_launch_us": round(avg_s * 1e6, 3),
+            "launches": n_sweep,
+        }
     exp_avg = max(exp_ms / 1e3 / max(n_exp, 1), 1e-12)
     exp_flop = 2.0 * inst.K * inst.K * inst.storage.S
     return {

@@ -95,33 +95,18 @@ int dp_abi_version(void);
 const char *dp_strerror(int code);
 const char *dp_last_error(void);
 
-/* Tuning hook: force the Bellman-sweep kernel and shape for later single solves in this
- * process.  NSPLIT >= 1: the per-row-tile kernel (one price state and a tile of SoC
- * indices per block) with R outputs per lane, D moves per chunk, NW waves per block and the
- * move range split over NSPLIT of them (NW % NSPLIT == 0).  NSPLIT = 0: the balanced
- * kernel (a row's output groups of R indices split into parts of equal work, each group's
- * chunks of D moves spread over lanes) with NW waves per block.  R = 0 restores the
- * built-in choice (the per-row-tile kernel with a shape chosen by the move window; the
- * balanced kernel, its shape and split chosen by a cost model, where no row tile fits the
- * LDS).  The choice never changes results:
- * every kernel and shape yields bitwise the same values and policies.  DP_EINVAL for a
+/* Tuning hook: force the Bellman-sweep tile shape for later solves in this process --
+ * R outputs per lane, D moves per chunk, NW waves per block, NSPLIT blocks of the move
+ * range (NW % NSPLIT == 0).  R = 0 restores the built-in choice.  The shape never changes
+ * results: every shape yields bitwise the same values and policies.  DP_EINVAL for a
  * shape this library has no kernel for; a later solve whose move window does not fit the
  * forced shape's LDS returns DP_ENOTSUP.  Not thread-safe with concurrent solves. */
 int dp_set_sweep_shape(int R, int D, int NW, int NSPLIT);
 
-/* The Bellman-sweep kernel and work split dp_solve uses for this problem (host only, no
- * GPU use).  Writes up to n ints into out and returns how many the whole plan has (or a
- * negative DP_E* code):
- *   balanced kernel:     1, R, D, threads per block, beta, LDS bytes, then (g0, g1, L)
- *                        for each of the beta parts of a row: output groups [g0, g1) (R SoC
- *                        indices each), each group's chunks of D moves spread over L lanes;
- *   per-row-tile kernel: 0, R, D, NW, NSPLIT, LDS bytes.
- * Follows dp_set_sweep_shape. */
-int dp_sweep_plan(const dp_problem *pb, int *out, int n);
-
 /* Measurement hook: while on (1, or 2 for events created without the system-scope
  * fence), dp_solve records a pair of HIP events on its stream around
- * every Bellman-sweep launch and every expectation launch.  dp_get_timing waits for the
+ * every stage launch (the Bellman sweep with its fused expectation; the expectation count
+ * stays 0).  dp_get_timing waits for the
  * recorded events, returns the summed elapsed milliseconds and launch counts of each
  * kind since the last call (or since dp_set_timing), and resets the record.  Host-side
  * state of this process; not thread-safe with concurrent solves. */

@@ -18,7 +18,7 @@ from . import _lib
 from ._lib import DPError, DP_STORE_V_ALL, DP_VALIDATE, check, lib, make_problem
 
 __all__ = ["solve", "solve_noalloc", "adjoint", "Solver", "DPFunction", "DPError",
-           "set_sweep_shape", "sweep_plan",
+           "set_sweep_shape",
            "BatchPlan", "kernel_timing", "solve_independent", "power_grid_size"]
 
 
@@ -79,21 +79,6 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
 def set_sweep_shape(R: int = 0, D: int = 0, NW: int = 0, NSPLIT: int = 0):
     """Force the sweep tile shape (tuning hook); no arguments restores the default."""
     check(lib().dp_set_sweep_shape(R, D, NW, NSPLIT))
-
-
-def sweep_plan(T: int, K: int, storage) -> dict:
-    """The Bellman-sweep kernel and work split a solve of this problem uses (host only)."""
-    pb = make_problem(T, K, storage)
-    L = lib()
-    n = L.dp_sweep_plan(ctypes.byref(pb), None, 0)
-    check(min(n, 0))
-    buf = (ctypes.c_int * n)()
-    check(min(L.dp_sweep_plan(ctypes.byref(pb), buf, n), 0))
-    v = list(buf)
-    if v[0] == 1:
-        return {"kernel": "balanced", "R": v[1], "D": v[2], "threads": v[3], "beta": v[4],
-                "lds": v[5], "parts": [tuple(v[6 + 3 * p: 9 + 3 * p]) for p in range(v[4])]}
-    return {"kernel": "row_tile", "R": v[1], "D": v[2], "NW": v[3], "NSPLIT": v[4], "lds": v[5]}
 
 
 def kernel_timing(on: Optional[bool] = None):

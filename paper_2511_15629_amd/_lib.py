@@ -29,8 +29,7 @@ EXPORTS = (
     "dp_abi_version", "dp_strerror", "dp_last_error", "dp_workspace_bytes", "dp_ckpt_bytes",
     "dp_solve", "dp_solve_noalloc", "dp_adjoint_workspace_bytes", "dp_adjoint", "dp_batch_plan_create",
     "dp_batch_solve", "dp_batch_solve_eager", "dp_batch_solve_looped", "dp_batch_plan_describe",
-    "dp_batch_plan_destroy", "dp_set_sweep_shape", "dp_sweep_plan", "dp_set_timing",
-    "dp_get_timing",
+    "dp_batch_plan_destroy", "dp_set_sweep_shape", "dp_set_timing", "dp_get_timing",
     "dp_iid_action_grid", "dp_iid_workspace_bytes", "dp_solve_iid",
 )
 
@@ -90,7 +89,6 @@ def lib():
             "dp_batch_plan_describe": ([p, ctypes.c_char_p, sz], i),
             "dp_batch_plan_destroy": ([p], None),
             "dp_set_sweep_shape": ([i, i, i, i], i),
-            "dp_sweep_plan": ([PP, ctypes.POINTER(i), i], i),
             "dp_set_timing": ([i], i),
             "dp_iid_action_grid": ([ctypes.POINTER(IidProblem), ctypes.POINTER(i),
                                     ctypes.POINTER(i), ctypes.POINTER(i)], i),

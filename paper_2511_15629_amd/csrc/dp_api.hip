@@ -7,11 +7,8 @@
 #include <stdio.h>
 #include <string.h>
 
-#include <algorithm>
-#include <map>
 #include <mutex>
 #include <string>
-#include <tuple>
 #include <vector>
 
 namespace {
@@ -46,7 +43,6 @@ using dpgpu::fail;
 using dpgpu::hip_fail;
 
 dpk::SweepShape g_shape_override = {0, 0, 0, 0};
-dpk::FlatShape g_flat_override = {0, 0, 0};
 
 // Optional per-kernel timing (dp_set_timing): HIP events recorded on the caller's stream
 // around every sweep and expectation launch of dp_solve.
@@ -98,7 +94,7 @@ int validate_problem(const dp_problem *pb)
     if (!(st.c_start >= 0.0f) || !isfinite(st.c_start)) return fail(DP_EINVAL, "c_start must be finite and >= 0");
     if (pb->flags & ~(uint32_t)(DP_STORE_V_ALL | DP_VALIDATE)) return fail(DP_EINVAL, "unknown flag bits 0x%x", pb->flags);
     if (pb->ckpt_every < 0) return fail(DP_EINVAL, "ckpt_every must be >= 0");
-    if (!choose_sweep(pb).ok)
+    if (pick_shape(pb).R == 0)
         return fail(DP_ENOTSUP, "move window %d..%d needs more LDS than a CU holds",
                     -st.w_down, st.w_up);
     return DP_OK;
@@ -106,7 +102,7 @@ int validate_problem(const dp_problem *pb)
 
 static bool fits(const dpk::SweepShape &sh, const dp_problem *pb)
 {
-    return dpk::sweep_lds_bytes(sh, pb->st.w_up, pb->st.w_down) <= 160 * 1024;
+    return dpk::sweep_lds_bytes(sh, pb->st.w_up, pb->st.w_down, pb->K) <= 160 * 1024;
 }
 
 dpk::SweepShape pick_shape(const dp_problem *pb)
@@ -125,146 +121,13 @@ dpk::SweepShape pick_shape(const dp_problem *pb)
     return fits(sh, pb) ? sh : none;
 }
 
-// ---- Balanced sweep planner --------------------------------------------------------
-// For a shape (R, D, NT) the row's groups are cut into beta parts of about equal work
-// (chunk count), each part's groups getting floor(NT / groups) lanes.  The cost model
-// counts, on the busiest SIMD, the chunk iterations of the waves it runs (a wave runs as
-// long as its longest lane; lanes are assigned slot-major as in the kernel) times the
-// instructions of one chunk (1.5 per candidate for the add and max, two per output for the
-// first raising chunk, a dozen for loads and the loop), plus a fixed cost per block;
-// blocks beyond one per CU stack on the same SIMDs.
-static double flat_unit_cost(const dpk::FlatShape &sh)
-{
-    return 1.5 * sh.R * sh.D + 2.0 * sh.R + 12.0;
-}
-
-static FlatPlan plan_flat_shape(const dp_problem *pb, const dpk::FlatShape &sh)
-{
-    FlatPlan best;
-    const int S = pb->st.S, wu = pb->st.w_up, wd = pb->st.w_down, K = pb->K;
-    const int R = sh.R, D = sh.D, NT = sh.NT;
-    const int G = (S + R - 1) / R;
-    std::vector<int> n(G);
-    std::vector<long long> pre(G + 1, 0);
-    for (int g = 0; g < G; ++g) {
-        int dlo4;
-        dpk::flat_group(g, R, D, S, wu, wd, dlo4, n[g]);
-        pre[g + 1] = pre[g] + n[g];
-    }
-    const long long U = pre[G];
-    const int beta_max = std::min(std::min(dpk::FLAT_MAX_PARTS, G), std::max(1, 2048 / K));
-    for (int beta = 1; beta <= beta_max; ++beta) {
-        FlatPlan fp;
-        fp.sh = sh;
-        fp.f.beta = beta;
-        int b_prev = 0;
-        double part_max = 0.0;
-        bool ok = true;
-        for (int p = 0; p < beta && ok; ++p) {
-            int b_next = G;
-            if (p + 1 < beta) {
-                const long long target = (U * (p + 1) + beta / 2) / beta;
-                b_next = (int)(std::lower_bound(pre.begin(), pre.end(), target) - pre.begin());
-            }
-            if (b_next <= b_prev || b_next > G) {
-                ok = false;
-                break;
-            }
-            const int g0 = b_prev, g1 = b_next, ngr = g1 - g0;
-            if (ngr > NT) {
-                ok = false;
-                break;
-            }
-            // L lanes per group, slot-major as in the kernel: lane t takes group t mod ngr
-            // and run slot t / ngr; the longer runs are in the first slots
-            const int Lg = NT / ngr;
-            double simd[4] = {0, 0, 0, 0};
-            for (int w = 0; w < NT / 64; ++w) {
-                int tw = 0;
-                for (int t = 64 * w; t < 64 * w + 64 && t < Lg * ngr; ++t) {
-                    const int nn = n[g0 + t % ngr], slot = t / ngr;
-                    const int c_lo = nn / Lg, rem = nn - c_lo * Lg;
-                    tw = std::max(tw, c_lo + (slot < rem ? 1 : 0));
-                }
-                simd[w % 4] += tw;
-            }
-            part_max = std::max(part_max, std::max(std::max(simd[0], simd[1]), std::max(simd[2], simd[3])));
-            const dpk::FlatLayout L = dpk::flat_layout(R, D, g0, g1, S, wu, wd);
-            fp.lds = std::max(fp.lds, dpk::flat_lds_bytes(sh, L));
-            if (fp.lds > 160 * 1024) ok = false;
-            fp.f.part[p] = dpk::FlatPart{g0, g1, Lg};
-            b_prev = b_next;
-        }
-        if (!ok) continue;
-        const int per_cu = (K * beta + 255) / 256;
-        // one wave per SIMD (a single 4-wave block per CU) hides LDS latency poorly
-        const double occ = (per_cu * NT / 256 >= 2) ? 1.0 : 1.35;
-        fp.cost = per_cu * (part_max * flat_unit_cost(sh) * occ + 400.0);
-        fp.ok = true;
-        if (fp.cost < best.cost) best = fp;
-    }
-    return best;
-}
-
-#define DP_FLAT_CANDIDATES {8, 16, 512}, {8, 16, 256}, {4, 16, 512}, {4, 16, 256}, {8, 8, 512}, {4, 8, 256}
-
-FlatPlan plan_flat(const dp_problem *pb)
-{
-    static std::mutex mu;
-    static std::map<std::tuple<int, int, int, int, int, int, int>, FlatPlan> cache;
-    const dpk::FlatShape ov = g_flat_override;
-    const auto key = std::make_tuple(pb->K, pb->st.S, pb->st.w_up, pb->st.w_down, ov.R, ov.D, ov.NT);
-    {
-        std::lock_guard<std::mutex> lk(mu);
-        auto it = cache.find(key);
-        if (it != cache.end()) return it->second;
-    }
-    FlatPlan best;
-    if (ov.R) {
-        best = plan_flat_shape(pb, ov);
-    } else {
-        const dpk::FlatShape cands[] = {DP_FLAT_CANDIDATES};
-        for (const auto &sh : cands) {
-            const FlatPlan fp = plan_flat_shape(pb, sh);
-            if (fp.ok && fp.cost < best.cost) best = fp;
-        }
-    }
-    std::lock_guard<std::mutex> lk(mu);
-    if (cache.size() > 256) cache.clear();
-    cache[key] = best;
-    return best;
-}
-
-SweepChoice choose_sweep(const dp_problem *pb)
-{
-    // The per-row-tile kernel is the default: on the day and year shapes its launches were
-    // measured faster than the balanced kernel's (the sweep there is bound by the first
-    // load's latency and the launch gaps, not by the busiest SIMD's work).  The balanced
-    // kernel runs when forced (dp_set_sweep_shape with NSPLIT = 0) or where no per-row tile
-    // fits the LDS.
-    SweepChoice c;
-    if (!g_flat_override.R) {
-        c.sh = pick_shape(pb);
-        if (c.sh.R != 0 || g_shape_override.R) {
-            c.ok = c.sh.R != 0;
-            return c;
-        }
-    }
-    c.fp = plan_flat(pb);
-    c.flat = c.ok = c.fp.ok;
-    return c;
-}
-
 SolveLayout solve_layout(const dp_problem *pb, size_t cap)
 {
     SolveLayout L = solve_layout(pb);
-    // a smaller ring of repacked P_t only launches the repacking more often
+    // a smaller ring of row sums only launches their computation more often
     while (L.total > cap && L.npk > 1) {
-        const int npk = L.npk >> 1;
-        L.Pp = L.flag + 256;
-        L.rho = L.Pp + align256((size_t)npk * sizeof(float) * dpk::packed_P_floats(pb->K));
-        L.total = L.rho + align256(sizeof(double) * (size_t)npk * pb->K);
-        L.npk = npk;
+        L.npk >>= 1;
+        L.total = L.rho + align256(sizeof(double) * (size_t)L.npk * pb->K);
     }
     return L;
 }
@@ -277,15 +140,10 @@ SolveLayout solve_layout(const dp_problem *pb)
     size_t o = 0;
     L.vA = o; o += plane;
     L.vB = o; o += plane;
-    L.W = o; o += plane;
     L.off = o; o += align256(sizeof(double) * ((size_t)pb->T + 2));
     L.flag = o; o += 256;
-    // P_t repacked for the expectation, up to 32 stages per pack launch (<= 64 MB)
-    const size_t pk = sizeof(float) * dpk::packed_P_floats(pb->K);
-    L.npk = 32;
-    while (L.npk > 1 && (size_t)L.npk * pk > ((size_t)64 << 20)) L.npk >>= 1;
-    if (L.npk > pb->T) L.npk = pb->T;
-    L.Pp = o; o += align256((size_t)L.npk * pk);
+    // rho_k - 1 of P_t, up to 32 stages per row-sum launch
+    L.npk = pb->T < 32 ? pb->T : 32;
     L.rho = o; o += align256(sizeof(double) * (size_t)L.npk * pb->K);
     L.total = o;
     return L;
@@ -319,7 +177,6 @@ int run_stages(const dp_problem *pb, int t_lo, int t_hi, const float *lam, const
     };
     char *base = static_cast<char *>(ws);
     float *vbuf[2] = {reinterpret_cast<float *>(base + L.vA), reinterpret_cast<float *>(base + L.vB)};
-    float *Wb = reinterpret_cast<float *>(base + L.W);
     double *off = reinterpret_cast<double *>(base + L.off);   // off[t] = C_t, t = t_lo..t_hi+1
     const size_t KS = (size_t)K * S;
     const int nst = t_hi - t_lo + 1;
@@ -330,44 +187,39 @@ int run_stages(const dp_problem *pb, int t_lo, int t_hi, const float *lam, const
     if (e != hipSuccess) return hip_fail(e, "init_terminal");
 
     const int E = out.ckpt_every > 0 ? out.ckpt_every : 16;
-    const SweepChoice ch = choose_sweep(pb);
-    if (!ch.ok)
+    const dpk::SweepShape sh = pick_shape(pb);
+    if (sh.R == 0)
         return fail(DP_ENOTSUP, "move window %d..%d needs more LDS than a CU holds",
                     -pb->st.w_down, pb->st.w_up);
-    if (!ch.flat && !dpk::sweep_shape_supported(ch.sh)) return fail(DP_EINVAL, "unsupported sweep shape");
+    if (!dpk::sweep_shape_supported(sh)) return fail(DP_EINVAL, "unsupported sweep shape");
+    // One launch per stage: each sweep block forms its own row of the expectation
+    // W_t = P_t V_{t+1} from the normalised V_{t+1} (fused; bitwise the tile chain).
     dpk::SweepArgs a;
-    a.ldw = L.Spad;
+    a.W = nullptr;
+    a.ldw = 0;
+    a.ldvn = L.Spad;
     a.K = K;
     a.S = S;
     a.w_up = pb->st.w_up;
     a.w_down = pb->st.w_down;
     a.pay = {pb->st.delta, pb->st.eta_c, pb->st.eta_d, pb->st.c_deg, pb->st.c_start};
-    a.W = Wb;
     a.ldv = L.Spad;
     int cur = 0;
-    float *Pp = reinterpret_cast<float *>(base + L.Pp);
-    double *rho = reinterpret_cast<double *>(base + L.rho);   // rho_k - 1 of the packed stages
-    const size_t pk = dpk::packed_P_floats(K);
-    int pk_lo = t_hi + 1;          // the packed stages are pk_lo .. pk_lo + npk - 1
+    double *rho = reinterpret_cast<double *>(base + L.rho);   // rho_k - 1 of stages pk_lo..
+    int pk_lo = t_hi + 1;          // the row sums held are of stages pk_lo .. pk_lo + npk - 1
     for (int t = t_hi; t >= t_lo; --t) {
         const float *vin = vbuf[cur];
         float *vout = vbuf[cur ^ 1];
-        if (t < pk_lo) {           // repack the next chunk of stages (downwards from t)
+        if (t < pk_lo) {           // row sums of the next chunk of stages (downwards from t)
             pk_lo = t - L.npk + 1 > t_lo ? t - L.npk + 1 : t_lo;
-            e = dpk::launch_pack_P(P + (size_t)(pk_lo - 1) * K * K, false, K, t - pk_lo + 1, Pp,
-                                   stream);
-            if (e == hipSuccess)
-                e = dpk::launch_row_sums(P + (size_t)(pk_lo - 1) * K * K, K, t - pk_lo + 1, rho,
-                                         stream);
-            if (e != hipSuccess) return hip_fail(e, "pack P");
+            e = dpk::launch_row_sums(P + (size_t)(pk_lo - 1) * K * K, K, t - pk_lo + 1, rho,
+                                     stream);
+            if (e != hipSuccess) return hip_fail(e, "row sums");
         }
-        if ((e = timer_mark(stream, 1, true)) != hipSuccess) return hip_fail(e, "timer");
-        e = dpk::launch_contract_packed(Pp + (size_t)(t - pk_lo) * pk, vin, L.Spad, Wb, L.Spad,
-                                        K, S, stream);
-        if (e != hipSuccess) return hip_fail(e, "contract");
-        if ((e = timer_mark(stream, 1, false)) != hipSuccess) return hip_fail(e, "timer");
+        a.Vn = vin;
+        a.Vn0 = vin;
         a.lam = lam + (size_t)(t - 1) * K;
-        a.P = nullptr;
+        a.P = P + (size_t)(t - 1) * K * K;
         a.rho1 = rho + (size_t)(t - pk_lo) * K;
         a.off_next = off + (t + 1);
         a.off_cur = off + t;
@@ -382,8 +234,7 @@ int run_stages(const dp_problem *pb, int t_lo, int t_hi, const float *lam, const
             a.ckpt_off = out.ckpt_off + (m - 1);
         }
         if ((e = timer_mark(stream, 0, true)) != hipSuccess) return hip_fail(e, "timer");
-        e = ch.flat ? dpk::launch_sweep_flat(a, ch.fp.sh, ch.fp.f, ch.fp.lds, stream)
-                    : dpk::launch_sweep(a, ch.sh, stream);
+        e = dpk::launch_sweep(a, sh, stream);
         if (e != hipSuccess) return hip_fail(e, "sweep");
         if ((e = timer_mark(stream, 0, false)) != hipSuccess) return hip_fail(e, "timer");
         cur ^= 1;
@@ -454,44 +305,12 @@ int dp_set_sweep_shape(int R, int D, int NW, int NSPLIT)
 {
     dpk::SweepShape sh = {R, D, NW, NSPLIT};
     if (R == 0) {
-        g_shape_override = dpk::SweepShape{0, 0, 0, 0};
-        g_flat_override = dpk::FlatShape{0, 0, 0};
-        return DP_OK;
-    }
-    if (NSPLIT == 0) {                 // the balanced kernel with NW waves per block
-        const dpk::FlatShape fs = {R, D, NW * 64};
-        if (!dpk::flat_shape_supported(fs))
-            return fail(DP_EINVAL, "unsupported balanced sweep shape %d,%d,%d", R, D, NW);
-        g_shape_override = dpk::SweepShape{0, 0, 0, 0};
-        g_flat_override = fs;
+        g_shape_override = sh;
         return DP_OK;
     }
     if (!dpk::sweep_shape_supported(sh)) return fail(DP_EINVAL, "unsupported sweep shape %d,%d,%d,%d", R, D, NW, NSPLIT);
     g_shape_override = sh;
-    g_flat_override = dpk::FlatShape{0, 0, 0};
     return DP_OK;
-}
-
-int dp_sweep_plan(const dp_problem *pb, int *out, int n)
-{
-    int rc = validate_problem(pb);
-    if (rc != DP_OK) return rc;
-    if (!out && n > 0) return fail(DP_EINVAL, "out is NULL");
-    const SweepChoice c = choose_sweep(pb);
-    std::vector<int> v;
-    if (c.flat) {
-        v = {1, c.fp.sh.R, c.fp.sh.D, c.fp.sh.NT, c.fp.f.beta, (int)c.fp.lds};
-        for (int p = 0; p < c.fp.f.beta; ++p) {
-            v.push_back(c.fp.f.part[p].g0);
-            v.push_back(c.fp.f.part[p].g1);
-            v.push_back(c.fp.f.part[p].L);
-        }
-    } else {
-        v = {0, c.sh.R, c.sh.D, c.sh.NW, c.sh.NSPLIT,
-             (int)dpk::sweep_lds_bytes(c.sh, pb->st.w_up, pb->st.w_down)};
-    }
-    for (int i = 0; i < n && i < (int)v.size(); ++i) out[i] = v[i];
-    return (int)v.size();
 }
 
 int dp_set_timing(int on)

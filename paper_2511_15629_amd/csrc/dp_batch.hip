@@ -369,8 +369,11 @@ int dp_batch_plan_create(dp_batch_plan **out, int n, const dp_problem *probs,
             destroy_plan(p);
             return fail(DP_EINVAL, "problem %d: batched solves take no flags or checkpoints", i);
         }
+        // the single solve's state plus the expectation plane W (the batch forms W_t in
+        // its own launches)
         p->region.push_back(total);
-        total += solve_layout(&p->probs[i]).total;
+        const SolveLayout Li = solve_layout(&p->probs[i]);
+        total += Li.total + ((sizeof(float) * (size_t)p->probs[i].K * Li.Spad + 255) & ~(size_t)255);
         p->Tmax = std::max(p->Tmax, p->probs[i].T);
     }
     int Kmax = 1;
@@ -414,7 +417,7 @@ int dp_batch_plan_create(dp_batch_plan **out, int n, const dp_problem *probs,
         d.pol = nullptr;
         d.vbuf0 = reinterpret_cast<float *>(base + L.vA);
         d.vbuf1 = reinterpret_cast<float *>(base + L.vB);
-        d.W = reinterpret_cast<float *>(base + L.W);
+        d.W = reinterpret_cast<float *>(base + L.total);
         d.off = reinterpret_cast<double *>(base + L.off);
         // K <= 128: one item = up to four 64-column panels over every row tile (P_t in
         // LDS); otherwise one item = a strip of four adjacent 16 x 16 tiles of one row tile

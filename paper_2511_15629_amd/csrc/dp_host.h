@@ -10,31 +10,13 @@ int hip_fail(hipError_t e, const char *what);
 int validate_problem(const dp_problem *pb);
 dpk::SweepShape pick_shape(const dp_problem *pb);
 
-// The balanced sweep's plan for a problem (cached per shape of the problem).
-struct FlatPlan {
-    bool ok = false;
-    dpk::FlatShape sh = {0, 0, 0};
-    dpk::FlatArgs f = {};
-    size_t lds = 0;
-    double cost = 1e300;
-};
-FlatPlan plan_flat(const dp_problem *pb);
-// The single solve's sweep: the balanced kernel when its plan fits (and no per-row-tile
-// shape is forced), else the per-row-tile kernel.
-struct SweepChoice {
-    bool ok = false, flat = false;
-    dpk::SweepShape sh = {0, 0, 0, 0};
-    FlatPlan fp;
-};
-SweepChoice choose_sweep(const dp_problem *pb);
-
 struct SolveLayout {
-    int Spad;                 // row stride of the value planes and the W plane
-    int npk;                  // stages of P_t held repacked for the expectation
-    size_t vA, vB, W, off, flag, Pp, rho, total;
+    int Spad;                 // row stride of the value planes
+    int npk;                  // stages whose row sums of P_t are held
+    size_t vA, vB, off, flag, rho, total;
 };
 SolveLayout solve_layout(const dp_problem *pb);
-// The same layout with the ring of repacked P_t shrunk until the total fits cap bytes (if it
+// The same layout with the ring of row sums shrunk until the total fits cap bytes (if it
 // can); results do not depend on the ring's size.
 SolveLayout solve_layout(const dp_problem *pb, size_t cap);
 

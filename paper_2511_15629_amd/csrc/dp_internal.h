@@ -13,10 +13,14 @@ struct Payoff {
 // One stage of the Bellman sweep (Eq. (5)): inputs W_t (expectation) and lam_t,
 // outputs the normalised values, optional absolute values, policies, checkpoint.
 struct SweepArgs {
-    const float *W;          // [K][ldw] expectation W_t; W[0] is the stage's normalisation
+    const float *W;          // [K][ldw] expectation W_t (when Vn is null)
     int ldw;
+    const float *Vn;         // [K][ldvn] normalised V_{t+1}: the block forms its W_t row
+    int ldvn;                //   itself (fused expectation; W unused); nullptr: read W
+    const float *Vn0;        // V_{t+1}[0][0] (normalised): the stage's normalisation constant
     const float *lam;        // [K]
-    const float *P;          // [K][K] P_t, for the row sums rho_k (nullable: rows sum to 1)
+    const float *P;          // [K][K] P_t: the fused expectation's rows, and the row sums
+                             // rho_k when rho1 is null (nullable then: rows sum to 1)
     const double *rho1;      // [K] rho_k - 1, precomputed (nullable: use P, or 0)
     int K, S, w_up, w_down;
     Payoff pay;
@@ -34,59 +38,6 @@ struct SweepShape {
     int R, D, NW, NSPLIT;    // outputs per lane, chunk of moves, waves per block, move splits
 };
 
-// Balanced Bellman sweep (sweep_flat_kernel): a row's SoC indices are cut into groups of
-// R outputs, each with its own move range in chunks of D moves; the groups of a row are
-// cut into `beta` parts (one block each) of about equal work.  Part p covers groups
-// [g0, g1) and gives each of them L lanes (L (g1 - g0) <= threads per block).
-constexpr int FLAT_MAX_PARTS = 64;
-struct FlatPart {
-    int g0, g1, L;
-};
-struct FlatArgs {
-    int beta;                          // parts (blocks) per row
-    FlatPart part[FLAT_MAX_PARTS];
-};
-struct FlatShape {
-    int R, D, NT;                      // outputs per lane, chunk of moves, threads per block
-};
-// The group geometry shared by the host planner and the kernel: group g covers outputs
-// [R g, min(R g + R, S)); its move range starts at dlo4 (the smallest feasible move of its
-// last output, rounded down to a multiple of 4) and has n chunks of D moves reaching the
-// largest feasible move of its first output.
-__host__ __device__ inline void flat_group(int g, int R, int D, int S, int w_up, int w_down,
-                                           int &dlo4, int &n)
-{
-    const int s0 = R * g;
-    const int s_last = (s0 + R < S ? s0 + R : S) - 1;
-    const int dlo = -w_down > -s_last ? -w_down : -s_last;
-    const int dhi = w_up < S - 1 - s0 ? w_up : S - 1 - s0;
-    dlo4 = dlo & ~3;
-    n = (dhi - dlo4 + D) / D;
-}
-// LDS layout of the block of groups [g0, g1): W segment [nW] from next state j_org (-inf
-// outside [0, S)) | reward row [nRw] from move r_org | u64 accumulators [ngr R].
-struct FlatLayout {
-    int j_org, r_org, nW, nRw, ngr;
-};
-__host__ __device__ inline FlatLayout flat_layout(int R, int D, int g0, int g1, int S, int w_up,
-                                                  int w_down)
-{
-    FlatLayout L;
-    int dlo0, n0, dloL, nL;
-    flat_group(g0, R, D, S, w_up, w_down, dlo0, n0);
-    flat_group(g1 - 1, R, D, S, w_up, w_down, dloL, nL);
-    L.j_org = R * g0 + dlo0;
-    L.r_org = dloL;                      // dlo4 does not increase with g
-    // every chunk load stays below R g + dlo4 + D n + R <= R g + w_up + D + R
-    L.nW = (R * (g1 - 1) + R + w_up + D - L.j_org + 4 + 3) & ~3;
-    L.nRw = (w_up + D - L.r_org + 3) & ~3;
-    L.ngr = g1 - g0;
-    return L;
-}
-bool flat_shape_supported(const FlatShape &sh);
-size_t flat_lds_bytes(const FlatShape &sh, const FlatLayout &L);
-hipError_t launch_sweep_flat(const SweepArgs &a, const FlatShape &sh, const FlatArgs &f,
-                             size_t lds, hipStream_t stream);
 // rho1[t][k] = (sum of row k of P_t, FP64, the sweep's fixed order) - 1 for nstage stages
 hipError_t launch_row_sums(const float *P, int K, int nstage, double *rho1, hipStream_t stream);
 
@@ -170,7 +121,7 @@ hipError_t launch_contract_packed(const float *Ap, const float *B, int ldb, floa
                                   int K, int N, hipStream_t stream);
 hipError_t launch_sweep(const SweepArgs &a, const SweepShape &sh, hipStream_t stream);
 int sweep_tile(const SweepShape &sh);       // outputs per block along s
-size_t sweep_lds_bytes(const SweepShape &sh, int w_up, int w_down);
+size_t sweep_lds_bytes(const SweepShape &sh, int w_up, int w_down, int K_fused = 0);
 bool sweep_shape_supported(const SweepShape &sh);
 
 // Initialise the normalised terminal state: vnorm = v_term (or 0, or a checkpoint),

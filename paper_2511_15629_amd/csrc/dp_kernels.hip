@@ -265,13 +265,101 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
     int *pc = reinterpret_cast<int *>(pb + NSPLIT * TS);
 
     const float NEG = -INFINITY;
+    float lam = 0.0f, shift = 0.0f;
+    double off_next = 0.0, rsum_m1 = 0.0;
+    if (a.Vn) {
+        // Fused expectation (the single solve): the block forms the row it needs,
+        // W_t[k][j] = sum_k' P_t[k][k'] V_{t+1}[k'][j] over the staged next states, from the
+        // normalised V_{t+1} and row k of P_t.  Each entry is an FP32 fma chain over k'
+        // ascending from 0, padded with zero terms to a multiple of 4: bitwise the MFMA tile
+        // chain of the expectation kernels.  A thread owns quads of four next states (one
+        // 16-byte load per row), with the next eight rows' loads in flight while eight are
+        // accumulated.
+        lam = a.lam[k];
+        shift = a.Vn[0];                           // the stage's normalisation V_{t+1}[0][0]
+        off_next = a.off_next[0];
+        rsum_m1 = a.rho1 ? a.rho1[k] : 0.0;
+        const int K = a.K, K4 = (K + 3) & ~3;
+        const float *Pk = a.P + (size_t)k * K;
+        // Row k of P_t goes to LDS (zero-padded to a multiple of 8), its loads issued before
+        // the first rows of V_{t+1}, and is read back as broadcasts.  Rows past K enter with
+        // P = 0 and the last row's values, adding exact zeros (the chain's sums are never
+        // -0), as the tile chain's padding does; quads outside [0, S) read row data at
+        // state 0 and are replaced by -inf.
+        constexpr int RB = 8;
+        const int K8 = (K + RB - 1) & ~(RB - 1);
+        float *prow = reinterpret_cast<float *>(pc + NSPLIT * TS);    // [K8]
+        const int jlo = s0 + dlo;                  // Wl[i] holds next state jlo + i
+        const int q0 = jlo >> 2;                   // quads of next states (floor: jlo < 0 ok)
+        const int q1 = (jlo + nwl + 3) >> 2;
+        float pmine[4];                            // this thread's first P entries
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = tid + u * NW * 64;
+            pmine[u] = i < K ? Pk[i] : 0.0f;
+        }
+        auto load = [&](float4 (&v)[RB], const float *vq, int r0) {
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const int kc = min(r0 + r, K - 1);
+                v[r] = *reinterpret_cast<const float4 *>(vq + (size_t)kc * a.ldvn);
+            }
+        };
+        float4 va[RB], vb[RB];
+        {
+            const int j0 = 4 * (q0 + tid);
+            load(va, a.Vn + ((j0 >= 0 && j0 < S) ? j0 : 0), 0);    // first quad's first rows
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = tid + u * NW * 64;
+            if (i < K8) prow[i] = pmine[u];
+        }
+        for (int i = tid + 4 * NW * 64; i < K8; i += NW * 64)   // rows beyond 4 per thread
+            prow[i] = i < K ? Pk[i] : 0.0f;
+        sweep_sync<NW>();
+        for (int q = q0 + tid; q < q1; q += NW * 64) {
+            const int j0 = 4 * q;
+            const bool in = j0 >= 0 && j0 < S;     // j0 < S <= ldvn: the quad is in the row
+            const float *vq = a.Vn + (in ? j0 : 0);
+            if (q != q0 + tid) load(va, vq, 0);
+            float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            auto accumulate = [&](const float4 (&v)[RB], int r0) {
+                const float4 *p4 = reinterpret_cast<const float4 *>(prow + r0);
+#pragma unroll
+                for (int r4 = 0; r4 < RB / 4; ++r4) {
+                    const float4 pp = p4[r4];
+                    const float pr[4] = {pp.x, pp.y, pp.z, pp.w};
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const float4 x = v[4 * r4 + r];
+                        acc.x = fmaf(pr[r], x.x, acc.x);
+                        acc.y = fmaf(pr[r], x.y, acc.y);
+                        acc.z = fmaf(pr[r], x.z, acc.z);
+                        acc.w = fmaf(pr[r], x.w, acc.w);
+                    }
+                }
+            };
+            for (int r0 = 0; r0 < K8; r0 += 2 * RB) {   // two batches per pass, no copies
+                if (r0 + RB < K8) load(vb, vq, r0 + RB);
+                accumulate(va, r0);
+                if (r0 + RB >= K8) break;
+                if (r0 + 2 * RB < K8) load(va, vq, r0 + 2 * RB);
+                accumulate(vb, r0 + RB);
+            }
+            const float av[4] = {acc.x, acc.y, acc.z, acc.w};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int j = j0 + c, i = j - jlo;
+                if (i >= 0 && i < nwl) Wl[i] = (j >= 0 && j < S) ? av[c] : NEG;
+            }
+        }
+    } else {
     // Every global value the block needs is requested before any is waited for, so the
     // block pays one memory round trip rather than one per dependent load: the W row over
     // the reachable next states (four loads per thread in flight), then lam_t[k], the
-    // stage's normalisation constant W_t[0][0] and the offset C_{t+1} (for the epilogue).
+    // stage's normalisation constant V_{t+1}[0][0] and the offset C_{t+1} (for the epilogue).
     const float *Wk = a.W + (size_t)k * a.ldw;
-    float lam = 0.0f, shift = 0.0f;
-    double off_next = 0.0, rsum_m1 = 0.0;
     for (int i4 = 0; i4 < nwl; i4 += 4 * NW * 64) {     // nwl > 0: at least one pass
         float w[4];
 #pragma unroll
@@ -283,7 +371,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
         if (i4 == 0) {
             __builtin_amdgcn_sched_barrier(0);      // the scalar loads go out after these
             lam = a.lam[k];
-            shift = a.W[0];
+            shift = a.Vn0[0];
             off_next = a.off_next[0];
             if (a.rho1) rsum_m1 = a.rho1[k];
             else if (a.P) rsum_m1 = row_sum_f64(a.P + (size_t)k * a.K, a.K, tid & 63) - 1.0;
@@ -293,6 +381,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
             const int i = i4 + u * NW * 64 + tid;
             if (i < nwl) Wl[i] = w[u];
         }
+    }
     }
     for (int i = tid; i < nrl; i += NW * 64) {
         const int d = dlo + i;
@@ -350,7 +439,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
     }
     sweep_sync<NW>();
 
-    const double Ct = off_next + (double)shift;   // shift = W_t[0][0], the normalisation
+    const double Ct = off_next + (double)shift;   // shift = V_{t+1}[0][0], the normalisation
     // W_t was formed from the normalised V_{t+1}; its true value adds rho_k C_{t+1}, of which
     // C_{t+1} is carried by the offset and (rho_k - 1) C_{t+1} goes into the row (exactly 0,
     // and skipped, when the row sums to 1)
@@ -399,14 +488,16 @@ __global__ __launch_bounds__(NW * 64) void sweep_kernel(SweepArgs a)
 
 int sweep_tile(const SweepShape &sh) { return 64 * sh.R * (sh.NW / sh.NSPLIT); }
 
-size_t sweep_lds_bytes(const SweepShape &sh, int w_up, int w_down)
+size_t sweep_lds_bytes(const SweepShape &sh, int w_up, int w_down, int K)
 {
+    // W row, reward row, partial maxima and chunks; with the fused expectation (K > 0)
+    // also row k of P_t padded to a multiple of 8
     const int TS = sweep_tile(sh);
     const int span = w_up + w_down + 1;
     const int nrl = ((span + sh.D - 1) / sh.D) * sh.D;
     const int nwl = (TS + nrl + sh.R + 3) & ~3;
     return sizeof(float) * ((size_t)nwl + nrl + (size_t)sh.NSPLIT * TS) +
-           sizeof(int) * (size_t)sh.NSPLIT * TS;
+           sizeof(int) * (size_t)sh.NSPLIT * TS + sizeof(float) * (size_t)((K + 7) & ~7);
 }
 
 #define DP_SWEEP_SHAPES(X) \
@@ -443,7 +534,7 @@ hipError_t launch_sweep(const SweepArgs &a, const SweepShape &sh, hipStream_t st
 {
     const int TS = sweep_tile(sh);
     dim3 grid((a.S + TS - 1) / TS, a.K);
-    const size_t lds = sweep_lds_bytes(sh, a.w_up, a.w_down);
+    const size_t lds = sweep_lds_bytes(sh, a.w_up, a.w_down, a.Vn ? a.K : 0);
 #define X(r, d, nw, ns)                                                                  \
     if (sh.R == r && sh.D == d && sh.NW == nw && sh.NSPLIT == ns) {                      \
         hipLaunchKernelGGL((sweep_kernel<r, d, nw, ns>), grid, dim3(nw * 64), lds, stream, \
@@ -451,225 +542,6 @@ hipError_t launch_sweep(const SweepArgs &a, const SweepShape &sh, hipStream_t st
         return hipGetLastError();                                                        \
     }
     DP_SWEEP_SHAPES(X)
-#undef X
-    return hipErrorInvalidValue;
-}
-
-// ------------------------------------------------------------------------------------
-// Balanced Bellman sweep (the default for the single solve).
-//
-// The SoC indices of a row (price state k) are cut into groups of R consecutive outputs.
-// Group g has its own move range (flat_group: from the smallest feasible move of its last
-// output, rounded down to a multiple of 4, to the largest of its first output) cut into
-// n_g chunks of D moves; a work unit is (group, chunk), R x D candidates.  Block (p, k)
-// takes the groups [g0, g1) of part p of row k (the host cuts each row into beta parts of
-// about equal work).  Each of its groups gets L lanes (the part's lane budget), lane
-// slot-major: lane t takes group t mod ngr and run slot t / ngr, so neighbouring lanes
-// read W R floats apart and the same reward entries.  A group's chunks are cut into L
-// contiguous runs differing by at most one chunk, the longer runs in the first slots, so
-// that most waves hold runs of one length (a wave runs as long as its longest lane).
-//
-// A lane keeps, per output, the running maximum of its chunks and the first chunk that
-// raised it (strict >, so equal later maxima keep the earlier chunk).  The lanes of a group
-// combine through a 64-bit LDS atomic max on (order-preserving bits of the value, inverted
-// chunk index): the largest value, and among equal values the smallest chunk.  The
-// winning chunk is then scanned once more for the first move whose recomputed candidate
-// equals the maximum bit for bit, which is the smallest next state attaining it.  The
-// maximum is exact and the candidates are formed from the same operands as in every other
-// sweep kernel, so values and policies are bitwise those of sweep_kernel.
-// ------------------------------------------------------------------------------------
-// Order-preserving map of a float to 32 bits (larger value -> larger key); -0 maps as +0.
-__device__ __forceinline__ unsigned flat_key(float v)
-{
-    const unsigned u = __float_as_uint(v + 0.0f);
-    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-}
-__device__ __forceinline__ float flat_unkey(unsigned k)
-{
-    return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
-}
-
-template <int R, int D, int NT>
-__global__ __launch_bounds__(NT) void sweep_flat_kernel(SweepArgs a, FlatArgs f)
-{
-    extern __shared__ float4 smem4[];
-    float *smem = reinterpret_cast<float *>(smem4);
-    constexpr int NWV = NT / 64;
-    const int p = blockIdx.x, k = blockIdx.y, tid = threadIdx.x;
-    const int S = a.S, w_up = a.w_up, w_down = a.w_down;
-    const int g0 = f.part[p].g0, g1 = f.part[p].g1, Lg = f.part[p].L;
-    const FlatLayout L = flat_layout(R, D, g0, g1, S, w_up, w_down);
-    const int ngr = L.ngr;
-    float *Wl = smem;
-    float *rl = Wl + L.nW;
-    unsigned long long *acc = reinterpret_cast<unsigned long long *>(rl + L.nRw);
-
-    const float NEG = -INFINITY;
-    // The W segment first (four loads per thread in flight), then the scalars: the block
-    // waits for one memory round trip.
-    const float *Wk = a.W + (size_t)k * a.ldw;
-    float lam = 0.0f, shift = 0.0f;
-    double off_next = 0.0, rsum_m1 = 0.0;
-    for (int i4 = 0; i4 < L.nW; i4 += 4 * NT) {
-        float w[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int i = i4 + u * NT + tid;
-            const int j = L.j_org + i;
-            w[u] = (i < L.nW && j >= 0 && j < S) ? Wk[j] : NEG;
-        }
-        if (i4 == 0) {
-            __builtin_amdgcn_sched_barrier(0);
-            lam = a.lam[k];
-            shift = a.W[0];
-            off_next = a.off_next[0];
-            if (a.rho1) rsum_m1 = a.rho1[k];
-            else if (a.P) rsum_m1 = row_sum_f64(a.P + (size_t)k * a.K, a.K, tid & 63) - 1.0;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int i = i4 + u * NT + tid;
-            if (i < L.nW) Wl[i] = w[u];
-        }
-    }
-    for (int i = tid; i < L.nRw; i += NT) {
-        const int d = L.r_org + i;
-        rl[i] = (d >= -w_down && d <= w_up) ? move_reward(lam, d, a.pay) : NEG;
-    }
-    for (int i = tid; i < ngr * R; i += NT) acc[i] = 0ull;
-
-    // This lane's group and run of chunks: slot-major order, so consecutive lanes take
-    // consecutive groups at the same run slot (their W reads are R floats apart, their
-    // reward reads coincide).  Group g's n chunks are cut into Lg runs, the n mod Lg longer
-    // ones (ceil(n / Lg) chunks) in the first slots.
-    const int gl = tid % ngr, slot = tid / ngr;
-    int c_begin = 0, cnt = 0, dlo4 = 0;
-    if (slot < Lg) {
-        int n;
-        flat_group(g0 + gl, R, D, S, w_up, w_down, dlo4, n);
-        const int c_lo = n / Lg, rem = n - c_lo * Lg;
-        cnt = c_lo + (slot < rem ? 1 : 0);
-        c_begin = slot * c_lo + min(slot, rem);
-    }
-    __syncthreads();
-
-    float best[R];
-    int cid[R];
-#pragma unroll
-    for (int i = 0; i < R; ++i) {
-        best[i] = NEG;
-        cid[i] = 0;
-    }
-    if (cnt > 0) {
-        const float *wsrc = Wl + (R * (g0 + gl) + dlo4 - L.j_org);
-        const float *rsrc0 = rl + (dlo4 - L.r_org);
-        for (int c = c_begin; c < c_begin + cnt; ++c) {
-            float w[R + D];
-            const float4 *src = reinterpret_cast<const float4 *>(wsrc + c * D);
-#pragma unroll
-            for (int m = 0; m < (R + D) / 4; ++m) {
-                const float4 v = src[m];
-                w[4 * m + 0] = v.x;
-                w[4 * m + 1] = v.y;
-                w[4 * m + 2] = v.z;
-                w[4 * m + 3] = v.w;
-            }
-            float r[D];
-            const float4 *rsrc = reinterpret_cast<const float4 *>(rsrc0 + c * D);
-#pragma unroll
-            for (int m = 0; m < D / 4; ++m) {
-                const float4 v = rsrc[m];
-                r[4 * m + 0] = v.x;
-                r[4 * m + 1] = v.y;
-                r[4 * m + 2] = v.z;
-                r[4 * m + 3] = v.w;
-            }
-#pragma unroll
-            for (int i = 0; i < R; ++i) {
-                float m = best[i];
-#pragma unroll
-                for (int d = 0; d < D; ++d) m = fmaxf(m, w[i + d] + r[d]);
-                cid[i] = (m > best[i]) ? c : cid[i];
-                best[i] = m;
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < R; ++i) {
-            if (best[i] > NEG) {
-                const unsigned long long key =
-                    ((unsigned long long)flat_key(best[i]) << 32) | (0xffffffffu - (unsigned)cid[i]);
-                atomicMax(&acc[gl * R + i], key);
-            }
-        }
-    }
-    __syncthreads();
-
-    const double Ct = off_next + (double)shift;
-    const double corr = rsum_m1 * off_next;
-    for (int o = tid; o < ngr * R; o += NT) {
-        const int gi = o / R, i = o - gi * R;
-        const int s = R * (g0 + gi) + i;
-        if (s >= S) continue;
-        const unsigned long long key = acc[o];
-        const float bv = flat_unkey((unsigned)(key >> 32));
-        const int bc = (int)(0xffffffffu - (unsigned)(key & 0xffffffffull));
-        int dlo4, n;
-        flat_group(g0 + gi, R, D, S, w_up, w_down, dlo4, n);
-        const float *wq = Wl + (R * (g0 + gi) + i + dlo4 + bc * D - L.j_org);
-        const float *rq = rl + (dlo4 + bc * D - L.r_org);
-        int arg = 0;
-#pragma unroll
-        for (int d = D - 1; d >= 0; --d) {
-            const float x = wq[d] + rq[d];
-            if (x == bv) arg = d;
-        }
-        const int j = s + dlo4 + bc * D + arg;
-        const float vn = corr == 0.0 ? bv - shift : (float)((double)(bv - shift) + corr);
-        const size_t idx = (size_t)k * S + s;
-        a.vnorm[(size_t)k * a.ldv + s] = vn;
-        if (a.vabs) __builtin_nontemporal_store((float)((double)vn + Ct), &a.vabs[idx]);
-        if (a.pol) __builtin_nontemporal_store((int16_t)j, &a.pol[idx]);
-        if (a.ckpt_v) __builtin_nontemporal_store(vn, &a.ckpt_v[idx]);
-    }
-    if (k == 0 && p == 0 && tid == 0) {
-        a.off_cur[0] = Ct;
-        if (a.ckpt_off) a.ckpt_off[0] = Ct;
-    }
-}
-
-#define DP_FLAT_SHAPES(X) \
-    X(8, 16, 512)         \
-    X(8, 16, 256)         \
-    X(4, 16, 512)         \
-    X(4, 16, 256)         \
-    X(8, 8, 512)          \
-    X(4, 8, 256)
-
-bool flat_shape_supported(const FlatShape &sh)
-{
-#define X(r, d, nt) \
-    if (sh.R == r && sh.D == d && sh.NT == nt) return true;
-    DP_FLAT_SHAPES(X)
-#undef X
-    return false;
-}
-
-size_t flat_lds_bytes(const FlatShape &sh, const FlatLayout &L)
-{
-    return sizeof(float) * ((size_t)L.nW + L.nRw) + sizeof(unsigned long long) * (size_t)L.ngr * sh.R;
-}
-
-hipError_t launch_sweep_flat(const SweepArgs &a, const FlatShape &sh, const FlatArgs &f,
-                             size_t lds, hipStream_t stream)
-{
-    if (lds > 160 * 1024) return hipErrorInvalidValue;
-    const dim3 grid(f.beta, a.K);
-#define X(r, d, nt)                                                                     \
-    if (sh.R == r && sh.D == d && sh.NT == nt) {                                        \
-        hipLaunchKernelGGL((sweep_flat_kernel<r, d, nt>), grid, dim3(nt), lds, stream, a, f); \
-        return hipGetLastError();                                                       \
-    }
-    DP_FLAT_SHAPES(X)
 #undef X
     return hipErrorInvalidValue;
 }
@@ -1031,6 +903,7 @@ __global__ __launch_bounds__(NW * 64 * tiles_per_block<NW>()) void batched_sweep
     a.lam = d.lam + (size_t)(t - 1) * d.K;
     a.P = d.P ? d.P + (size_t)(t - 1) * d.K * d.K : nullptr;
     a.rho1 = nullptr;
+    a.Vn = nullptr;
     a.K = d.K;
     a.S = d.S;
     a.w_up = d.w_up;
@@ -1038,6 +911,7 @@ __global__ __launch_bounds__(NW * 64 * tiles_per_block<NW>()) void batched_sweep
     a.pay = d.pay;
     const int cur = (d.T - t) & 1;
     a.vnorm = cur ? d.vbuf0 : d.vbuf1;
+    a.Vn0 = cur ? d.vbuf1 : d.vbuf0;          // V_{t+1}, read by this stage's expectation
     a.ldv = d.ld;
     a.off_next = d.off + (t + 1);
     a.off_cur = d.off + t;
