@@ -392,6 +392,9 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--extra", default="day,adjoint,batch,table3,cpu",
                     help="comma-separated extras to run after the headline line's steps")
+    ap.add_argument("--stages", type=int, default=0,
+                    help="profiling aid: solve only the workload's first N stages (counter runs "
+                         "serialise every launch); the JSON line then names the truncated workload")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the steps, copy 256 MiB device-to-device once (a kernel of known "
                          "traffic for calibrating hardware byte counters)")
@@ -410,6 +413,10 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     inst = wl.WORKLOADS[args.workload]()
+    if 0 < args.stages < inst.T:
+        import dataclasses
+        inst = dataclasses.replace(inst, name=f"{inst.name}_first{args.stages}", T=args.stages,
+                                   lam=inst.lam[:args.stages], P=inst.P[:args.stages])
     clock = ClockSampler(torch)
     sec, timing = timed_solves(dp, torch, inst, args.steps, args.warmup, clock)
     cand = inst.candidates()

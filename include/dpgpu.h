@@ -96,12 +96,12 @@ const char *dp_strerror(int code);
 const char *dp_last_error(void);
 
 /* Tuning hook: force the Bellman-sweep tile shape for later solves in this process --
- * R outputs per lane, D moves per chunk, NW waves per block, NSPLIT blocks of the move
- * range (NW % NSPLIT == 0).  R = 0 restores the built-in choice.  The shape never changes
- * results: every shape yields bitwise the same values and policies.  DP_EINVAL for a
- * shape this library has no kernel for; a later solve whose move window does not fit the
- * forced shape's LDS returns DP_ENOTSUP.  Not thread-safe with concurrent solves. */
-int dp_set_sweep_shape(int R, int D, int NW, int NSPLIT);
+ * `tile` SoC indices per block (a multiple of 64, 64..1024) on `waves` waves (1, 2, 4 or
+ * 8).  tile = 0 restores the built-in choice.  The shape never changes results: every
+ * shape yields bitwise the same values and policies.  DP_EINVAL for a shape this library
+ * has no kernel for; a later solve whose move window does not fit the forced shape's LDS
+ * returns DP_ENOTSUP.  Not thread-safe with concurrent solves. */
+int dp_set_sweep_shape(int tile, int waves);
 
 /* Measurement hook: while on (1, or 2 for events created without the system-scope
  * fence), dp_solve records a pair of HIP events on its stream around

@@ -76,9 +76,10 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
 
 
-def set_sweep_shape(R: int = 0, D: int = 0, NW: int = 0, NSPLIT: int = 0):
-    """Force the sweep tile shape (tuning hook); no arguments restores the default."""
-    check(lib().dp_set_sweep_shape(R, D, NW, NSPLIT))
+def set_sweep_shape(tile: int = 0, waves: int = 0):
+    """Force the sweep tile shape -- `tile` SoC indices per block on `waves` waves (tuning
+    hook); no arguments restores the default."""
+    check(lib().dp_set_sweep_shape(tile, waves))
 
 
 def kernel_timing(on: Optional[bool] = None):

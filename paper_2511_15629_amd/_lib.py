@@ -88,7 +88,7 @@ def lib():
             "dp_batch_solve_looped": ([p, p, p, p, p, p], i),
             "dp_batch_plan_describe": ([p, ctypes.c_char_p, sz], i),
             "dp_batch_plan_destroy": ([p], None),
-            "dp_set_sweep_shape": ([i, i, i, i], i),
+            "dp_set_sweep_shape": ([i, i], i),
             "dp_set_timing": ([i], i),
             "dp_iid_action_grid": ([ctypes.POINTER(IidProblem), ctypes.POINTER(i),
                                     ctypes.POINTER(i), ctypes.POINTER(i)], i),

@@ -42,7 +42,7 @@ namespace {
 using dpgpu::fail;
 using dpgpu::hip_fail;
 
-dpk::SweepShape g_shape_override = {0, 0, 0, 0};
+dpk::SweepShape g_shape_override = {0, 0};
 
 // Optional per-kernel timing (dp_set_timing): HIP events recorded on the caller's stream
 // around every sweep and expectation launch of dp_solve.
@@ -94,7 +94,7 @@ int validate_problem(const dp_problem *pb)
     if (!(st.c_start >= 0.0f) || !isfinite(st.c_start)) return fail(DP_EINVAL, "c_start must be finite and >= 0");
     if (pb->flags & ~(uint32_t)(DP_STORE_V_ALL | DP_VALIDATE)) return fail(DP_EINVAL, "unknown flag bits 0x%x", pb->flags);
     if (pb->ckpt_every < 0) return fail(DP_EINVAL, "ckpt_every must be >= 0");
-    if (pick_shape(pb).R == 0)
+    if (pick_shape(pb).TS == 0)
         return fail(DP_ENOTSUP, "move window %d..%d needs more LDS than a CU holds",
                     -st.w_down, st.w_up);
     return DP_OK;
@@ -107,17 +107,15 @@ static bool fits(const dpk::SweepShape &sh, const dp_problem *pb)
 
 dpk::SweepShape pick_shape(const dp_problem *pb)
 {
-    const dpk::SweepShape none{0, 0, 0, 0};
-    if (g_shape_override.R) return fits(g_shape_override, pb) ? g_shape_override : none;
-    const int span = pb->st.w_up + pb->st.w_down + 1;
-    // Long move ranges: 8 outputs per lane, the range split over 8 waves (measured best
-    // on the 100 x 1001 and 50 x 2001 grids); short ranges: fewer splits.  Windows too wide
-    // for those tiles' LDS fall back to one wave of 256 outputs (the least LDS per span).
-    dpk::SweepShape sh = span >= 256 ? dpk::SweepShape{8, 16, 8, 8}
-                         : span >= 64 ? dpk::SweepShape{4, 16, 4, 4}
-                                      : dpk::SweepShape{4, 8, 4, 2};
+    const dpk::SweepShape none{0, 0};
+    if (g_shape_override.TS) return fits(g_shape_override, pb) ? g_shape_override : none;
+    // Tiles of 512 SoC indices on eight waves: one block per CU for the 50 x 2001 and
+    // 100 x 1001 grids, whose blocks are bound by staging the expectation row (the halo of
+    // a tile is its move window, so a wider tile re-reads less of it per output).  Windows
+    // too wide for that LDS fall back to 64 outputs on one wave (the least LDS per span).
+    dpk::SweepShape sh = dpk::SweepShape{512, 8};
     if (fits(sh, pb)) return sh;
-    sh = dpk::SweepShape{4, 8, 1, 1};
+    sh = dpk::SweepShape{64, 1};
     return fits(sh, pb) ? sh : none;
 }
 
@@ -188,7 +186,7 @@ int run_stages(const dp_problem *pb, int t_lo, int t_hi, const float *lam, const
 
     const int E = out.ckpt_every > 0 ? out.ckpt_every : 16;
     const dpk::SweepShape sh = pick_shape(pb);
-    if (sh.R == 0)
+    if (sh.TS == 0)
         return fail(DP_ENOTSUP, "move window %d..%d needs more LDS than a CU holds",
                     -pb->st.w_down, pb->st.w_up);
     if (!dpk::sweep_shape_supported(sh)) return fail(DP_EINVAL, "unsupported sweep shape");
@@ -299,16 +297,17 @@ const char *dp_strerror(int code)
 
 const char *dp_last_error(void) { return g_last_error.c_str(); }
 
-// Tuning hook: force the sweep tile shape (R outputs per lane, D moves per chunk, NW waves
-// per block, NSPLIT move splits); R = 0 restores the built-in choice.
-int dp_set_sweep_shape(int R, int D, int NW, int NSPLIT)
+// Tuning hook: force the sweep tile shape (tile outputs per block, waves per block);
+// tile = 0 restores the built-in choice.
+int dp_set_sweep_shape(int tile, int waves)
 {
-    dpk::SweepShape sh = {R, D, NW, NSPLIT};
-    if (R == 0) {
-        g_shape_override = sh;
+    dpk::SweepShape sh = {tile, waves};
+    if (tile == 0) {
+        g_shape_override = dpk::SweepShape{0, 0};
         return DP_OK;
     }
-    if (!dpk::sweep_shape_supported(sh)) return fail(DP_EINVAL, "unsupported sweep shape %d,%d,%d,%d", R, D, NW, NSPLIT);
+    if (!dpk::sweep_shape_supported(sh))
+        return fail(DP_EINVAL, "unsupported sweep shape: tile %d, %d waves", tile, waves);
     g_shape_override = sh;
     return DP_OK;
 }

@@ -28,11 +28,10 @@ using namespace dpgpu;
 
 namespace {
 
+// (tile outputs, waves per block)
 const dpk::SweepShape kCandidates[] = {
-    {8, 16, 8, 8}, {4, 16, 8, 8}, {8, 16, 4, 4}, {4, 16, 4, 4}, {8, 8, 4, 4}, {4, 8, 4, 2},
-    {4, 16, 8, 4}, {8, 16, 4, 2}, {8, 8, 4, 1},  {4, 8, 4, 1},  {8, 16, 4, 1}, {4, 16, 4, 1},
-    {4, 4, 4, 1},  {8, 4, 4, 1},  {4, 8, 2, 1},  {4, 4, 2, 1},  {4, 8, 1, 1},  {8, 8, 1, 1},
-    {4, 4, 1, 1},
+    {512, 8}, {256, 8}, {512, 4}, {256, 4}, {128, 4}, {512, 2},
+    {256, 2}, {128, 2}, {512, 1}, {256, 1}, {128, 1}, {64, 1},
 };
 
 // Instances fall into independent groups, one branch of the graph each.  Panel class c
@@ -71,7 +70,7 @@ bool shape_fits(const dpk::SweepShape &sh, int w_up, int w_down)
 std::string shape_str(const dpk::SweepShape &sh)
 {
     char b[64];
-    snprintf(b, sizeof b, "%d %d %d %d", sh.R, sh.D, sh.NW, sh.NSPLIT);
+    snprintf(b, sizeof b, "%d %d", sh.TS, sh.NW);
     return b;
 }
 
@@ -185,14 +184,13 @@ static int enqueue_all(dp_batch_plan *p, hipStream_t s)
     return DP_OK;
 }
 
-// Built-in sweep shape of a span class when no tuning is asked for: the shapes the tuner
-// picks for the five-minute fleet (one- and two-wave tiles of 256 and 512 outputs for short
-// rows, where a 1024-output tile leaves lanes idle on row tails), else the single solve's.
+// Built-in sweep shape of a span class when no tuning is asked for: short windows take
+// small blocks (many instances' rows in flight per CU), long ones the single solve's tile.
 static dpk::SweepShape batch_default_shape(const dp_problem *pb, int span_hi)
 {
-    dpk::SweepShape sh = span_hi <= 64    ? dpk::SweepShape{4, 8, 1, 1}
-                         : span_hi <= 256 ? dpk::SweepShape{4, 8, 2, 1}
-                         : span_hi <= 512 ? dpk::SweepShape{4, 16, 4, 1}
+    dpk::SweepShape sh = span_hi <= 64    ? dpk::SweepShape{256, 1}
+                         : span_hi <= 256 ? dpk::SweepShape{256, 2}
+                         : span_hi <= 512 ? dpk::SweepShape{512, 4}
                                           : pick_shape(pb);
     return sh;
 }
@@ -312,9 +310,10 @@ static std::map<int, dpk::SweepShape> read_cache(const char *path)
     char line[256];
     while (fgets(line, sizeof line, f)) {
         if (line[0] == '#') continue;
-        int b, r, d, nw, ns;
-        if (sscanf(line, "%d %d %d %d %d", &b, &r, &d, &nw, &ns) == 5) {
-            dpk::SweepShape sh = {r, d, nw, ns};
+        // "bucket tile waves  # comment"; lines of any other form are skipped
+        int b, ts, nw, extra;
+        if (sscanf(line, "%d %d %d %d", &b, &ts, &nw, &extra) == 3) {
+            dpk::SweepShape sh = {ts, nw};
             if (dpk::sweep_shape_supported(sh)) m[b] = sh;
         }
     }
@@ -544,8 +543,8 @@ int dp_batch_plan_create(dp_batch_plan **out, int n, const dp_problem *probs,
              n, p->Tmax, p->n_pitems, p->n_citems, p->ws_bytes);
     p->text = buf;
     for (auto &c : p->classes) {
-        snprintf(buf, sizeof buf, "  class span %d..%d: shape R=%d D=%d NW=%d NSPLIT=%d, %zu instances, %zu blocks/stage, %zu B LDS%s\n",
-                 c.span_lo, c.span_hi, c.sh.R, c.sh.D, c.sh.NW, c.sh.NSPLIT, c.inst.size(),
+        snprintf(buf, sizeof buf, "  class span %d..%d: tile %d on %d waves, %zu instances, %zu blocks/stage, %zu B LDS%s\n",
+                 c.span_lo, c.span_hi, c.sh.TS, c.sh.NW, c.inst.size(),
                  c.items.size(), c.lds, c.tuned_us >= 0 ? " (autotuned)" : "");
         p->text += buf;
     }

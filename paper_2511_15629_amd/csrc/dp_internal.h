@@ -35,7 +35,7 @@ struct SweepArgs {
 };
 
 struct SweepShape {
-    int R, D, NW, NSPLIT;    // outputs per lane, chunk of moves, waves per block, move splits
+    int TS, NW;              // outputs per block (SoC tile), waves per block
 };
 
 // rho1[t][k] = (sum of row k of P_t, FP64, the sweep's fixed order) - 1 for nstage stages

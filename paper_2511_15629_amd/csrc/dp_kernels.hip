@@ -203,21 +203,39 @@ hipError_t launch_contract_packed(const float *Ap, const float *B, int ldb, floa
 
 
 // ------------------------------------------------------------------------------------
-// Max-plus Bellman sweep with argmax (Algorithm 1: gather, -inf mask, payoff, max).
+// Max-plus Bellman sweep with argmax (Eq. (5); Algorithm 1's gather, -inf mask, payoff and
+// maximum over the action axis), evaluated as exact sliding-window maxima.
 //
-// Block = one price state k and a tile of TS consecutive SoC indices.  The expectation
-// row W_t[k][.] for every next state the tile can reach is staged in LDS with -inf
-// outside [0, S) (the infeasibility mask), together with the reward row r(lam, d) for the
-// tile's move range (-inf past its end).  Each lane owns R consecutive outputs; the move
-// range is cut into chunks of D moves and the chunks are split over NSPLIT waves.
+// The payoff of a move of d grid steps is affine in d on each side of the idle move
+// (Eq. (1) with the transition of Eq. (2)): r(d) = A_c d - c_start for d > 0 with
+// A_c = -(lam + c_deg) delta / eta_c, and r(d) = A_d d - c_start for d < 0 with
+// A_d = -(lam - c_deg) delta eta_d.  So for output s the charge candidates
+// W[j] + r(j - s), j = s + 1 .. s + w_up, are u_c[j] - A_c s - c_start with
+// u_c[j] = W[j] + A_c j: the best of them is the maximum of u_c over a window of w_up
+// consecutive next states, the same window shape for every s.  The discharge side is the
+// window j = s - w_down .. s - 1 of u_d[j] = W[j] + A_d j, and the idle move is W[s].
+// Next states outside [0, S) carry W = -inf (the infeasibility mask).
 //
-// Inner loop: per output and chunk, the running maximum absorbs D candidates
-// (an add and a max each; pairs of maxima fold into v_max3), and the index of the
-// first chunk that raised the maximum is kept.  After the waves' partial results are
-// merged (lowest move range first, strict >), the winning chunk is scanned once more
-// to find the first move whose candidate equals the maximum: candidates are recomputed
-// from the same operands, so the equality is exact, and "first chunk, then first move
-// within it" is the smallest next state attaining the maximum.
+// Maxima over windows of a fixed width w (van Herk; Gil and Werman): cut the next-state
+// axis into segments of w.  A window starting at e covers the end of e's segment and the
+// start of the next one, so its maximum is the larger of the suffix maximum of e's
+// segment from e and the prefix maximum of the next segment up to e + w - 1.  Prefix and
+// suffix maxima are segmented scans: a lane scans a run of 8 next states, the runs of a
+// wave are joined by a segmented shuffle scan, and consecutive passes of a wave by a carry.
+// Each output then reads two table entries per side instead of w candidates.
+//
+// Decisions.  u is formed in FP32 by one fma at the absolute next state j, so every output
+// ranks the same u values whatever tile it belongs to: results do not depend on the tiling
+// or on the launch.  Within a side the smallest next state attaining the maximum of u is
+// taken (prefix scans keep the earlier entry on ties, suffix scans the later-scanned,
+// smaller one, and a window's suffix part wins over its prefix part).  The side's
+// candidate is then re-evaluated in FP64 as W[j] + r(j - s), and the sides are compared in
+// next-state order -- discharge (j < s), idle (j = s), charge (j > s) -- each later one
+// only when strictly larger.  The value is rounded to FP32 once, from that FP64 candidate.
+// Ranking by the rounded u can prefer a candidate within the rounding of |W| + |A j| of
+// the exact maximum (a near-tie); the value carried on is that candidate's own.
+//
+// Block = one price state k and a tile of TS consecutive SoC indices, on NW waves.
 // ------------------------------------------------------------------------------------
 // Sum of the K entries of a row of P_t in FP64, the same in every wave and every kernel:
 // lane l adds entries l, l + 64, ... in ascending order, then a xor butterfly (each step
@@ -242,27 +260,170 @@ __device__ __forceinline__ void sweep_sync()
         __syncthreads();
 }
 
-// smem: this tile's LDS (sweep_lds_bytes); tid: thread index within the tile's NW waves.
-template <int R, int D, int NW, int NSPLIT>
-__device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, const int tile,
-                                            float *smem, const int tid)
-{
-    constexpr int NS = NW / NSPLIT;
-    constexpr int TS = 64 * R * NS;
+// A candidate of the window scans: its u value and its position e in the side's array
+// (value -inf: none).
+struct Cand {
+    float v;
+    int e;
+};
 
+// The better of a (earlier in scan order) and b; TIE_A: a tie keeps a.
+template <bool TIE_A>
+__device__ __forceinline__ Cand better(const Cand &a, const Cand &b)
+{
+    const bool keep_a = TIE_A ? (a.v >= b.v) : (a.v > b.v);
+    return keep_a ? a : b;
+}
+
+// Payoff slopes of Eq. (1) per grid step on the charge and discharge sides, FP64.
+__device__ __forceinline__ double slope_charge(float lam, const Payoff &p)
+{
+    return -((double)lam + (double)p.c_deg) * (double)p.delta / (double)p.eta_c;
+}
+__device__ __forceinline__ double slope_discharge(float lam, const Payoff &p)
+{
+    return -((double)lam - (double)p.c_deg) * (double)p.delta * (double)p.eta_d;
+}
+
+// LDS index of entry e of a scan array: one spare word after every 8, so that 64 lanes
+// holding runs of 8 consecutive entries touch 64 different banks.
+__host__ __device__ __forceinline__ int pad8(int e) { return e + (e >> 3); }
+
+// Layout of a side with w moves over a tile of TS outputs (n = TS + w - 1 entries): the u
+// array, unpadded, -inf from n up to un = n rounded up to 8 (the scans' range); then the
+// prefix table g, indexed by e - glo(w) over TS + 16 entries (glo: w - 1 rounded down to
+// 8), and the suffix table h, indexed by e over the same count; entries are (value,
+// position) pairs at pair index pad8(i).
+__host__ __device__ __forceinline__ int scan_un(int TS, int w) { return (TS + w - 1 + 7) & ~7; }
+__host__ __device__ __forceinline__ int scan_glo(int w) { return (w - 1) & ~7; }
+__host__ __device__ __forceinline__ int scan_tab_words(int TS) { return 2 * pad8(TS + 16); }
+
+// Words of a side's LDS (0 for a side without moves); a multiple of 8.
+__host__ __device__ __forceinline__ int side_words(int TS, int w)
+{
+    if (w == 0) return 0;
+    return scan_un(TS, w) + 2 * scan_tab_words(TS);
+}
+
+// Scan-order absorption of candidate (v, e) into acc: a segment boundary (head) starts
+// anew; otherwise acc keeps its candidate unless v is larger (FWD: acc holds the smaller
+// positions, ties keep it) or at least as large (backward: v has the smaller position).
+// Written as one predicate and two selects.
+template <bool FWD>
+__device__ __forceinline__ void absorb(Cand &acc, float v, int e, bool head)
+{
+    const bool take = head | (FWD ? v > acc.v : v >= acc.v);
+    acc.v = take ? v : acc.v;
+    acc.e = take ? e : acc.e;
+}
+
+// One step of a segmented inclusive scan across the wave's lanes: lane l takes the
+// candidate of the lane the DPP control names (unless a segment boundary already lies in
+// the lanes it covers), and the boundary flags are or-ed.  Lanes without a source lane,
+// or outside the row mask, see (-inf, -1, no boundary).
+template <bool FWD, int CTRL, int ROWS>
+__device__ __forceinline__ void dpp_scan_step(Cand &acc, int &flag)
+{
+    const float ov = __int_as_float(__builtin_amdgcn_update_dpp(
+        (int)0xff800000, __float_as_int(acc.v), CTRL, ROWS, 0xf, false));
+    const int oe = __builtin_amdgcn_update_dpp(-1, acc.e, CTRL, ROWS, 0xf, false);
+    const int of = __builtin_amdgcn_update_dpp(0, flag, CTRL, ROWS, 0xf, false);
+    // the other lane's candidate is earlier in scan order: it wins ties forward
+    const bool take = !flag & (FWD ? ov >= acc.v : ov > acc.v);
+    acc.v = take ? ov : acc.v;
+    acc.e = take ? oe : acc.e;
+    flag |= of;
+}
+
+// One wave's segmented max-scan of u[e] over e in [r0, r1) (both multiples of 8), whose
+// segments are [phi + m w, phi + (m + 1) w) cut to the range (the range starts and ends
+// segments).  FWD: prefix maxima g(e) over [segment start, e], written at tg[pad8(e - glo)]
+// for runs inside [glo, glo + TS + 16); otherwise suffix maxima h(e) over [e, segment end],
+// written at tg[pad8(e)] for runs inside [0, TS).
+// Lane l of a pass holds the run of 8 entries t = p0 + 8 l .. p0 + 8 l + 7 in scan order
+// (e = r0 + t forward, r1 - 1 - t backward).  A first pass over the run gives the lane's
+// total; DPP row shifts within rows of 16 lanes and row broadcasts of lanes 15 and 31
+// join the lanes' totals; a second pass rescans the run from the lane's exclusive prefix.
+template <bool FWD>
+__device__ __forceinline__ void window_scan(const float *__restrict__ u, int un, int w, int phi,
+                                            int r0, int r1, int glo, int TS,
+                                            float *__restrict__ tg, int lane)
+{
+    const Cand none = {-INFINITY, -1};
+    const int len = r1 - r0;
+    Cand carry = none;                         // inclusive result at the previous pass's end
+    for (int p0 = 0; p0 < len; p0 += 512) {
+        const int t0 = p0 + 8 * lane;
+        // the run's entries (its first entry e0; lanes past the range read in-bounds data
+        // and come after every lane of the range in scan order)
+        const int e0 = FWD ? r0 + t0 : r1 - 1 - t0;
+        float x[8];
+        {
+            const int lo = FWD ? min(e0, un - 8) : max(e0, 7) - 7;
+            const float4 a4 = *reinterpret_cast<const float4 *>(u + lo);
+            const float4 b4 = *reinterpret_cast<const float4 *>(u + lo + 4);
+            const float y[8] = {a4.x, a4.y, a4.z, a4.w, b4.x, b4.y, b4.z, b4.w};
+#pragma unroll
+            for (int q = 0; q < 8; ++q) x[q] = y[FWD ? q : 7 - q];
+        }
+        // segment boundaries in the run: bit q when entry q starts a segment in scan order
+        int mask = t0 == 0 ? 1 : 0;
+        {
+            const int dm = FWD ? e0 - phi : phi - 1 - e0;      // entry q: dm + q = 0 mod w
+            int r = dm % w;
+            r = r < 0 ? r + w : r;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                mask |= (r == 0) << q;
+                r = r + 1 == w ? 0 : r + 1;
+            }
+        }
+        Cand acc = lane == 0 ? carry : none;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) absorb<FWD>(acc, x[q], FWD ? e0 + q : e0 - q, (mask >> q) & 1);
+        int flag = mask != 0;
+        dpp_scan_step<FWD, 0x111, 0xf>(acc, flag);     // row_shr:1
+        dpp_scan_step<FWD, 0x112, 0xf>(acc, flag);     // row_shr:2
+        dpp_scan_step<FWD, 0x114, 0xf>(acc, flag);     // row_shr:4
+        dpp_scan_step<FWD, 0x118, 0xf>(acc, flag);     // row_shr:8
+        dpp_scan_step<FWD, 0x142, 0xa>(acc, flag);     // row_bcast:15 into rows 1, 3
+        dpp_scan_step<FWD, 0x143, 0xc>(acc, flag);     // row_bcast:31 into rows 2, 3
+        // the lane's exclusive prefix (wave_shr:1); lane 0 continues the previous pass
+        Cand run = {__int_as_float(__builtin_amdgcn_update_dpp(
+                        (int)0xff800000, __float_as_int(acc.v), 0x138, 0xf, 0xf, false)),
+                    __builtin_amdgcn_update_dpp(-1, acc.e, 0x138, 0xf, 0xf, false)};
+        if (lane == 0) run = carry;
+        carry = Cand{__int_as_float(__builtin_amdgcn_readlane(__float_as_int(acc.v), 63)),
+                     __builtin_amdgcn_readlane(acc.e, 63)};
+        // runs lie wholly inside or outside the written ranges (all bounds are multiples
+        // of 8)
+        const int i0 = FWD ? e0 - glo : e0 - 7;
+        if (t0 < len && i0 >= 0 && i0 < (FWD ? TS + 16 : TS)) {
+            float2 *out = reinterpret_cast<float2 *>(tg) + pad8(i0);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                absorb<FWD>(run, x[q], FWD ? e0 + q : e0 - q, (mask >> q) & 1);
+                out[FWD ? q : 7 - q] = make_float2(run.v, __int_as_float(run.e));
+            }
+        }
+    }
+}
+
+// smem: this tile's LDS (sweep_lds_bytes); tid: thread index within the tile's NW waves.
+// LDS: per side (discharge, then charge) the u array and the g and h tables; the
+// expectation row over next states s0 - w_down .. s0 + TS - 1 + w_up; with the fused
+// expectation, row k of P_t.
+template <int NW>
+__device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, const int tile,
+                                            const int TS, float *smem, const int tid)
+{
     const int s0 = tile * TS;
-    const int S = a.S;
-    const int s_end = min(s0 + TS, S);
-    const int dlo = max(-a.w_down, -(s_end - 1));
-    const int dhi = min(a.w_up, S - 1 - s0);
-    const int span = dhi - dlo + 1;
-    const int nchunk = (span + D - 1) / D;
-    const int nrl = nchunk * D;
-    const int nwl = (TS + nrl + R + 3) & ~3;
-    float *Wl = smem;
-    float *rl = smem + nwl;
-    float *pb = rl + nrl;
-    int *pc = reinterpret_cast<int *>(pb + NSPLIT * TS);
+    const int S = a.S, w_up = a.w_up, w_down = a.w_down;
+    const int jlo = s0 - w_down;                        // Wl[i] holds next state jlo + i
+    const int nwl = TS + w_down + w_up;
+    const int wd_words = side_words(TS, w_down), tp2 = pad8(TS + 16);
+    float *const side_d = smem, *const side_c = smem + wd_words;   // discharge, charge
+    float *Wl = smem + wd_words + side_words(TS, w_up);
 
     const float NEG = -INFINITY;
     float lam = 0.0f, shift = 0.0f;
@@ -279,7 +440,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
         shift = a.Vn[0];                           // the stage's normalisation V_{t+1}[0][0]
         off_next = a.off_next[0];
         rsum_m1 = a.rho1 ? a.rho1[k] : 0.0;
-        const int K = a.K, K4 = (K + 3) & ~3;
+        const int K = a.K;
         const float *Pk = a.P + (size_t)k * K;
         // Row k of P_t goes to LDS (zero-padded to a multiple of 8), its loads issued before
         // the first rows of V_{t+1}, and is read back as broadcasts.  Rows past K enter with
@@ -288,8 +449,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
         // state 0 and are replaced by -inf.
         constexpr int RB = 8;
         const int K8 = (K + RB - 1) & ~(RB - 1);
-        float *prow = reinterpret_cast<float *>(pc + NSPLIT * TS);    // [K8]
-        const int jlo = s0 + dlo;                  // Wl[i] holds next state jlo + i
+        float *prow = Wl + ((nwl + 3) & ~3);       // [K8]
         const int q0 = jlo >> 2;                   // quads of next states (floor: jlo < 0 ok)
         const int q1 = (jlo + nwl + 3) >> 2;
         float pmine[4];                            // this thread's first P entries
@@ -355,121 +515,131 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
             }
         }
     } else {
-    // Every global value the block needs is requested before any is waited for, so the
-    // block pays one memory round trip rather than one per dependent load: the W row over
-    // the reachable next states (four loads per thread in flight), then lam_t[k], the
-    // stage's normalisation constant V_{t+1}[0][0] and the offset C_{t+1} (for the epilogue).
-    const float *Wk = a.W + (size_t)k * a.ldw;
-    for (int i4 = 0; i4 < nwl; i4 += 4 * NW * 64) {     // nwl > 0: at least one pass
-        float w[4];
+        // Every global value the block needs is requested before any is waited for, so the
+        // block pays one memory round trip rather than one per dependent load: the W row
+        // over the reachable next states (four loads per thread in flight), then lam_t[k],
+        // the stage's normalisation constant V_{t+1}[0][0] and the offset C_{t+1}.
+        const float *Wk = a.W + (size_t)k * a.ldw;
+        for (int i4 = 0; i4 < nwl; i4 += 4 * NW * 64) {     // nwl > 0: at least one pass
+            float w[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int i = i4 + u * NW * 64 + tid;
-            const int j = s0 + dlo + i;
-            w[u] = (i < nwl && j >= 0 && j < S) ? Wk[j] : NEG;
-        }
-        if (i4 == 0) {
-            __builtin_amdgcn_sched_barrier(0);      // the scalar loads go out after these
-            lam = a.lam[k];
-            shift = a.Vn0[0];
-            off_next = a.off_next[0];
-            if (a.rho1) rsum_m1 = a.rho1[k];
-            else if (a.P) rsum_m1 = row_sum_f64(a.P + (size_t)k * a.K, a.K, tid & 63) - 1.0;
-        }
+            for (int u = 0; u < 4; ++u) {
+                const int i = i4 + u * NW * 64 + tid;
+                const int j = jlo + i;
+                w[u] = (i < nwl && j >= 0 && j < S) ? Wk[j] : NEG;
+            }
+            if (i4 == 0) {
+                __builtin_amdgcn_sched_barrier(0);      // the scalar loads go out after these
+                lam = a.lam[k];
+                shift = a.Vn0[0];
+                off_next = a.off_next[0];
+                if (a.rho1) rsum_m1 = a.rho1[k];
+                else if (a.P) rsum_m1 = row_sum_f64(a.P + (size_t)k * a.K, a.K, tid & 63) - 1.0;
+            }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int i = i4 + u * NW * 64 + tid;
-            if (i < nwl) Wl[i] = w[u];
+            for (int u = 0; u < 4; ++u) {
+                const int i = i4 + u * NW * 64 + tid;
+                if (i < nwl) Wl[i] = w[u];
+            }
         }
-    }
-    }
-    for (int i = tid; i < nrl; i += NW * 64) {
-        const int d = dlo + i;
-        rl[i] = (d <= dhi) ? move_reward(lam, d, a.pay) : NEG;
     }
     sweep_sync<NW>();
 
-    const int wave = tid >> 6, lane = tid & 63;
-    const int ws = wave % NS, wsp = wave / NS;
-    const int c_begin = (wsp * nchunk) / NSPLIT;
-    const int c_end = ((wsp + 1) * nchunk) / NSPLIT;
-    const int base = (ws * 64 + lane) * R;
+    // u arrays of both sides: discharge e = 0 .. TS + w_down - 2 at next state
+    // s0 - w_down + e (Wl[e]); charge e = 0 .. TS + w_up - 2 at next state s0 + 1 + e
+    // (Wl[w_down + 1 + e]); -inf up to the arrays' rounded length.  Output o's window is
+    // e = o .. o + w - 1 on either side.
+    const double A_d = slope_discharge(lam, a.pay), A_c = slope_charge(lam, a.pay);
+    {
+        const float Ad = (float)A_d, Ac = (float)A_c;
+        const int nd = w_down ? TS + w_down - 1 : 0, nc = w_up ? TS + w_up - 1 : 0;
+        const int ud = w_down ? scan_un(TS, w_down) : 0, uc = w_up ? scan_un(TS, w_up) : 0;
+        for (int e = tid; e < ud; e += NW * 64)
+            side_d[e] = e < nd ? fmaf(Ad, (float)(jlo + e), Wl[e]) : NEG;
+        for (int e = tid; e < uc; e += NW * 64)
+            side_c[e] = e < nc ? fmaf(Ac, (float)(s0 + 1 + e), Wl[w_down + 1 + e]) : NEG;
+    }
+    sweep_sync<NW>();
 
-    float best[R];
-    int cid[R];
-#pragma unroll
-    for (int i = 0; i < R; ++i) {
-        best[i] = NEG;
-        cid[i] = -1;
-    }
-    for (int c = c_begin; c < c_end; ++c) {
-        float w[R + D];
-        const float4 *src = reinterpret_cast<const float4 *>(Wl + base + c * D);
-#pragma unroll
-        for (int m = 0; m < (R + D) / 4; ++m) {
-            const float4 v = src[m];
-            w[4 * m + 0] = v.x;
-            w[4 * m + 1] = v.y;
-            w[4 * m + 2] = v.z;
-            w[4 * m + 3] = v.w;
+    // Prefix and suffix maxima.  Tasks 0..3 = g_d, h_d, g_c, h_c; with four or more waves
+    // each task has NW / 4 waves (two of them split the array at a segment boundary that is
+    // a multiple of 8, the segments shifted by phi to make one), with fewer the waves take
+    // turns.  Output o reads h(o) and g(o + w - 1).
+    {
+        const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+        constexpr int G = NW >= 8 ? 2 : 1;
+        for (int task = NW >= 4 ? wave / (NW / 4) : wave; task < 4; task += NW >= 4 ? 4 : NW) {
+            const int sd = task >> 1;
+            const int w = sd ? w_up : w_down;
+            if (w == 0) continue;
+            const int n = TS + w - 1, un = scan_un(TS, w);
+            float *const u = sd ? side_c : side_d;
+            float *tg = u + un + (task & 1) * scan_tab_words(TS);
+            // split point: a segment boundary phi + m w near n / 2 that is a multiple of 8
+            int phi = 0, split = un;
+            if (G == 2 && w >= 8) {
+                const int m = max(1, (n + w) / (2 * w));
+                phi = (8 - (m * w) % 8) % 8;
+                if (phi + m * w < un) split = phi + m * w;
+            }
+            const int gw = NW >= 8 ? wave % 2 : 0;
+            if (gw == 1 && split == un) continue;
+            const int r0 = gw ? split : 0, r1 = (gw || G == 1) ? un : split;
+            if (task & 1)
+                window_scan<false>(u, un, w, phi, r0, r1, 0, TS, tg, lane);
+            else
+                window_scan<true>(u, un, w, phi, r0, r1, scan_glo(w), TS, tg, lane);
         }
-        float r[D];
-        const float4 *rsrc = reinterpret_cast<const float4 *>(rl + c * D);
-#pragma unroll
-        for (int m = 0; m < D / 4; ++m) {
-            const float4 v = rsrc[m];
-            r[4 * m + 0] = v.x;
-            r[4 * m + 1] = v.y;
-            r[4 * m + 2] = v.z;
-            r[4 * m + 3] = v.w;
-        }
-#pragma unroll
-        for (int i = 0; i < R; ++i) {
-            float m = best[i];
-#pragma unroll
-            for (int d = 0; d < D; ++d) m = fmaxf(m, w[i + d] + r[d]);
-            cid[i] = (m > best[i]) ? c : cid[i];
-            best[i] = m;
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < R; ++i) {
-        pb[wsp * TS + base + i] = best[i];
-        pc[wsp * TS + base + i] = cid[i];
     }
     sweep_sync<NW>();
 
     const double Ct = off_next + (double)shift;   // shift = V_{t+1}[0][0], the normalisation
     // W_t was formed from the normalised V_{t+1}; its true value adds rho_k C_{t+1}, of which
-    // C_{t+1} is carried by the offset and (rho_k - 1) C_{t+1} goes into the row (exactly 0,
-    // and skipped, when the row sums to 1)
-    const double corr = rsum_m1 * off_next;
+    // C_{t+1} is carried by the offset and (rho_k - 1) C_{t+1} goes into the row (exactly 0
+    // when the row sums to 1)
+    const double corr = rsum_m1 * off_next - (double)shift;
+    const double cst = (double)a.pay.c_start;
     for (int o = tid; o < TS; o += NW * 64) {
         const int s = s0 + o;
         if (s >= S) break;
-        float bv = NEG;
-        int bc = 0;
-#pragma unroll
-        for (int p = 0; p < NSPLIT; ++p) {
-            const float v = pb[p * TS + o];
-            if (v > bv) {
-                bv = v;
-                bc = pc[p * TS + o];
+        // best candidate of each side: the window's suffix part (smaller next states)
+        // wins a tie with its prefix part; j - jlo is the candidate's Wl index
+        double best = -INFINITY;
+        int bj = s;
+        if (w_down) {
+            const float2 *t = reinterpret_cast<const float2 *>(side_d + scan_un(TS, w_down));
+            const float2 h = t[tp2 + pad8(o)], g = t[pad8(o + w_down - 1 - scan_glo(w_down))];
+            const Cand m = better<true>(Cand{h.x, __float_as_int(h.y)},
+                                        Cand{g.x, __float_as_int(g.y)});
+            if (m.v > NEG) {
+                best = (double)Wl[m.e] + A_d * (double)(m.e - w_down - o) - cst;
+                bj = jlo + m.e;
             }
         }
-        int arg = 0;
-#pragma unroll
-        for (int d = D - 1; d >= 0; --d) {
-            const float x = Wl[o + bc * D + d] + rl[bc * D + d];
-            if (x == bv) arg = d;
+        const double idle = (double)Wl[o + w_down];
+        if (!(best >= idle)) {
+            best = idle;
+            bj = s;
         }
-        const int j = s + dlo + bc * D + arg;
-        const float vn = corr == 0.0 ? bv - shift : (float)((double)(bv - shift) + corr);
+        if (w_up) {
+            const float2 *t = reinterpret_cast<const float2 *>(side_c + scan_un(TS, w_up));
+            const float2 h = t[tp2 + pad8(o)], g = t[pad8(o + w_up - 1 - scan_glo(w_up))];
+            const Cand m = better<true>(Cand{h.x, __float_as_int(h.y)},
+                                        Cand{g.x, __float_as_int(g.y)});
+            if (m.v > NEG) {
+                const double v = (double)Wl[w_down + 1 + m.e] + A_c * (double)(m.e + 1 - o) - cst;
+                if (v > best) {
+                    best = v;
+                    bj = s0 + 1 + m.e;
+                }
+            }
+        }
+        const float vn = (float)(best + corr);
         const size_t idx = (size_t)k * S + s;
         a.vnorm[(size_t)k * a.ldv + s] = vn;
         // outputs the next launch does not read go out as non-temporal stores
         if (a.vabs) __builtin_nontemporal_store((float)((double)vn + Ct), &a.vabs[idx]);
-        if (a.pol) __builtin_nontemporal_store((int16_t)j, &a.pol[idx]);
+        if (a.pol) __builtin_nontemporal_store((int16_t)bj, &a.pol[idx]);
         if (a.ckpt_v) __builtin_nontemporal_store(vn, &a.ckpt_v[idx]);
     }
     if (k == 0 && tile == 0 && tid == 0) {
@@ -478,70 +648,49 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
     }
 }
 
-template <int R, int D, int NW, int NSPLIT>
-__global__ __launch_bounds__(NW * 64) void sweep_kernel(SweepArgs a)
+template <int NW>
+__global__ __launch_bounds__(NW * 64) void sweep_kernel(SweepArgs a, int TS)
 {
     extern __shared__ float4 smem4[];
-    sweep_block<R, D, NW, NSPLIT>(a, blockIdx.y, blockIdx.x, reinterpret_cast<float *>(smem4),
-                                  threadIdx.x);
+    sweep_block<NW>(a, blockIdx.y, blockIdx.x, TS, reinterpret_cast<float *>(smem4),
+                    threadIdx.x);
 }
 
-int sweep_tile(const SweepShape &sh) { return 64 * sh.R * (sh.NW / sh.NSPLIT); }
+int sweep_tile(const SweepShape &sh) { return sh.TS; }
 
 size_t sweep_lds_bytes(const SweepShape &sh, int w_up, int w_down, int K)
 {
-    // W row, reward row, partial maxima and chunks; with the fused expectation (K > 0)
-    // also row k of P_t padded to a multiple of 8
-    const int TS = sweep_tile(sh);
-    const int span = w_up + w_down + 1;
-    const int nrl = ((span + sh.D - 1) / sh.D) * sh.D;
-    const int nwl = (TS + nrl + sh.R + 3) & ~3;
-    return sizeof(float) * ((size_t)nwl + nrl + (size_t)sh.NSPLIT * TS) +
-           sizeof(int) * (size_t)sh.NSPLIT * TS + sizeof(float) * (size_t)((K + 7) & ~7);
+    // both sides' u arrays and window tables, the expectation row over the tile's windows
+    // (a multiple of 4 entries), and with the fused expectation (K > 0) row k of P_t padded
+    // to a multiple of 8
+    const size_t nwl = ((size_t)sh.TS + w_up + w_down + 3) & ~(size_t)3;
+    return sizeof(float) * ((size_t)side_words(sh.TS, w_down) + side_words(sh.TS, w_up) + nwl +
+                            (size_t)((K + 7) & ~7));
 }
 
-#define DP_SWEEP_SHAPES(X) \
-    X(8, 16, 4, 4)         \
-    X(8, 16, 8, 8)         \
-    X(4, 16, 8, 8)         \
-    X(4, 16, 4, 4)         \
-    X(8, 8, 4, 4)          \
-    X(4, 8, 4, 2)          \
-    X(8, 16, 4, 2)         \
-    X(4, 16, 8, 4)         \
-    X(8, 8, 4, 1)          \
-    X(4, 8, 4, 1)          \
-    X(8, 16, 4, 1)         \
-    X(4, 16, 4, 1)         \
-    X(4, 4, 4, 1)          \
-    X(8, 4, 4, 1)          \
-    X(4, 8, 2, 1)          \
-    X(4, 4, 2, 1)          \
-    X(4, 8, 1, 1)          \
-    X(8, 8, 1, 1)          \
-    X(4, 4, 1, 1)
+// waves per block with a kernel, and the tile sizes (outputs per block) allowed
+#define DP_SWEEP_WAVES(X) X(1) X(2) X(4) X(8)
 
 bool sweep_shape_supported(const SweepShape &sh)
 {
-#define X(r, d, nw, ns) \
-    if (sh.R == r && sh.D == d && sh.NW == nw && sh.NSPLIT == ns) return true;
-    DP_SWEEP_SHAPES(X)
+    if (sh.TS < 64 || sh.TS > 1024 || sh.TS % 64) return false;
+#define X(nw) \
+    if (sh.NW == nw) return true;
+    DP_SWEEP_WAVES(X)
 #undef X
     return false;
 }
 
 hipError_t launch_sweep(const SweepArgs &a, const SweepShape &sh, hipStream_t stream)
 {
-    const int TS = sweep_tile(sh);
-    dim3 grid((a.S + TS - 1) / TS, a.K);
+    dim3 grid((a.S + sh.TS - 1) / sh.TS, a.K);
     const size_t lds = sweep_lds_bytes(sh, a.w_up, a.w_down, a.Vn ? a.K : 0);
-#define X(r, d, nw, ns)                                                                  \
-    if (sh.R == r && sh.D == d && sh.NW == nw && sh.NSPLIT == ns) {                      \
-        hipLaunchKernelGGL((sweep_kernel<r, d, nw, ns>), grid, dim3(nw * 64), lds, stream, \
-                           a);                                                           \
-        return hipGetLastError();                                                        \
+#define X(nw)                                                                               \
+    if (sh.NW == nw) {                                                                      \
+        hipLaunchKernelGGL((sweep_kernel<nw>), grid, dim3(nw * 64), lds, stream, a, sh.TS); \
+        return hipGetLastError();                                                           \
     }
-    DP_SWEEP_SHAPES(X)
+    DP_SWEEP_WAVES(X)
 #undef X
     return hipErrorInvalidValue;
 }
@@ -881,10 +1030,10 @@ hipError_t launch_iid_stage(const IidArgs &a_in, hipStream_t stream)
 template <int NW>
 constexpr int tiles_per_block() { return NW == 1 ? 4 : 1; }
 
-template <int R, int D, int NW, int NSPLIT>
+template <int NW>
 __global__ __launch_bounds__(NW * 64 * tiles_per_block<NW>()) void batched_sweep_kernel(
     const BatchDesc *__restrict__ desc, const SweepItem *__restrict__ items, int n, int tau,
-    int lds_tile)
+    int lds_tile, int TS)
 {
     extern __shared__ float4 smem4[];
     constexpr int TPB = tiles_per_block<NW>();
@@ -919,9 +1068,9 @@ __global__ __launch_bounds__(NW * 64 * tiles_per_block<NW>()) void batched_sweep
     a.pol = d.pol ? d.pol + (size_t)(t - 1) * d.K * d.S : nullptr;
     a.ckpt_v = nullptr;
     a.ckpt_off = nullptr;
-    sweep_block<R, D, NW, NSPLIT>(a, it.k, it.tile,
-                                  reinterpret_cast<float *>(smem4) + (size_t)slot * lds_tile,
-                                  TPB > 1 ? (int)(threadIdx.x & 63) : (int)threadIdx.x);
+    sweep_block<NW>(a, it.k, it.tile, TS,
+                    reinterpret_cast<float *>(smem4) + (size_t)slot * lds_tile,
+                    TPB > 1 ? (int)(threadIdx.x & 63) : (int)threadIdx.x);
 }
 
 __global__ __launch_bounds__(256) void batched_contract_kernel(const BatchDesc *__restrict__ desc,
@@ -1153,15 +1302,15 @@ hipError_t launch_batched_sweep(const BatchDesc *desc, const SweepItem *items, i
     // lds: one tile's bytes; a block of tiles_per_block tiles gets one 16-byte aligned
     // slice each
     const int lds_tile = (int)(((lds + 15) & ~(size_t)15) / sizeof(float));
-#define X(r, d, nw, ns)                                                                      \
-    if (sh.R == r && sh.D == d && sh.NW == nw && sh.NSPLIT == ns) {                          \
+#define X(nw)                                                                                \
+    if (sh.NW == nw) {                                                                       \
         constexpr int tpb = tiles_per_block<nw>();                                           \
-        hipLaunchKernelGGL((batched_sweep_kernel<r, d, nw, ns>), dim3((n + tpb - 1) / tpb),  \
+        hipLaunchKernelGGL((batched_sweep_kernel<nw>), dim3((n + tpb - 1) / tpb),            \
                            dim3(nw * 64 * tpb), (size_t)lds_tile * sizeof(float) * tpb,      \
-                           stream, desc, items, n, tau, lds_tile);                           \
+                           stream, desc, items, n, tau, lds_tile, sh.TS);                    \
         return hipGetLastError();                                                            \
     }
-    DP_SWEEP_SHAPES(X)
+    DP_SWEEP_WAVES(X)
 #undef X
     return hipErrorInvalidValue;
 }

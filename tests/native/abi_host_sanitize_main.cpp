@@ -75,7 +75,7 @@ int main()
     // a window too wide for any tile's LDS
     dp_problem w = good();
     w.st.S = DP_MAX_S;
-    w.st.w_up = w.st.w_down = 15000;
+    w.st.w_up = w.st.w_down = 12000;
     EXPECT(dp_workspace_bytes(&w) == 0);
     // missing pointers, small or misaligned workspace: rejected before device work
     EXPECT(dp_solve(&pb, NULL, (float *)256, NULL, (float *)256, NULL, NULL, (void *)256, ws, NULL) == DP_EINVAL);
@@ -113,9 +113,11 @@ int main()
     EXPECT(dp_batch_plan_describe(NULL, buf, sizeof buf) == DP_EINVAL);
     dp_batch_plan_destroy(NULL);
     // tuning hooks (host state only)
-    EXPECT(dp_set_sweep_shape(3, 3, 3, 3) == DP_EINVAL);
-    EXPECT(dp_set_sweep_shape(8, 16, 8, 8) == DP_OK);
-    EXPECT(dp_set_sweep_shape(0, 0, 0, 0) == DP_OK);
+    EXPECT(dp_set_sweep_shape(96, 4) == DP_EINVAL);
+    EXPECT(dp_set_sweep_shape(512, 3) == DP_EINVAL);
+    EXPECT(dp_set_sweep_shape(2048, 8) == DP_EINVAL);
+    EXPECT(dp_set_sweep_shape(512, 8) == DP_OK);
+    EXPECT(dp_set_sweep_shape(0, 0) == DP_OK);
     printf(bad ? "FAILED\n" : "ok\n");
     return bad;
 }
