@@ -28,10 +28,12 @@ using namespace dpgpu;
 
 namespace {
 
-// (tile outputs, waves per block)
+// (tile outputs, waves per block).  A scan pass covers 512 next states per wave, and a
+// tile of TS outputs with w moves per side scans TS + w - 1 of them: tiles of 448 (960)
+// keep windows up to 64 in one (two) passes.
 const dpk::SweepShape kCandidates[] = {
-    {512, 8}, {256, 8}, {512, 4}, {256, 4}, {128, 4}, {512, 2},
-    {256, 2}, {128, 2}, {512, 1}, {256, 1}, {128, 1}, {64, 1},
+    {512, 8}, {960, 8}, {448, 8}, {512, 4}, {448, 4}, {256, 4}, {448, 2},
+    {256, 2}, {192, 2}, {448, 1}, {256, 1}, {192, 1}, {128, 1}, {64, 1},
 };
 
 // Instances fall into independent groups, one branch of the graph each.  Panel class c
@@ -188,8 +190,8 @@ static int enqueue_all(dp_batch_plan *p, hipStream_t s)
 // small blocks (many instances' rows in flight per CU), long ones the single solve's tile.
 static dpk::SweepShape batch_default_shape(const dp_problem *pb, int span_hi)
 {
-    dpk::SweepShape sh = span_hi <= 64    ? dpk::SweepShape{256, 1}
-                         : span_hi <= 256 ? dpk::SweepShape{256, 2}
+    dpk::SweepShape sh = span_hi <= 128   ? dpk::SweepShape{448, 1}
+                         : span_hi <= 256 ? dpk::SweepShape{448, 2}
                          : span_hi <= 512 ? dpk::SweepShape{512, 4}
                                           : pick_shape(pb);
     return sh;

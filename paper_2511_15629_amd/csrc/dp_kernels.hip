@@ -285,18 +285,22 @@ __device__ __forceinline__ double slope_discharge(float lam, const Payoff &p)
     return -((double)lam - (double)p.c_deg) * (double)p.delta * (double)p.eta_d;
 }
 
-// LDS index of entry e of a scan array: one spare word after every 8, so that 64 lanes
-// holding runs of 8 consecutive entries touch 64 different banks.
-__host__ __device__ __forceinline__ int pad8(int e) { return e + (e >> 3); }
-
 // Layout of a side with w moves over a tile of TS outputs (n = TS + w - 1 entries): the u
-// array, unpadded, -inf from n up to un = n rounded up to 8 (the scans' range); then the
-// prefix table g, indexed by e - glo(w) over TS + 16 entries (glo: w - 1 rounded down to
-// 8), and the suffix table h, indexed by e over the same count; entries are (value,
-// position) pairs at pair index pad8(i).
+// array, -inf from n up to un = n rounded up to 8 (the scans' range); then the prefix
+// table g, indexed by e - glo(w) over TS + 16 entries (glo: w - 1 rounded down to 8), and
+// the suffix table h, indexed by e over the same count.  A table entry is the position of
+// the maximum (16 bits: positions stay below 2^15); its value is u at that position.
 __host__ __device__ __forceinline__ int scan_un(int TS, int w) { return (TS + w - 1 + 7) & ~7; }
 __host__ __device__ __forceinline__ int scan_glo(int w) { return (w - 1) & ~7; }
-__host__ __device__ __forceinline__ int scan_tab_words(int TS) { return 2 * pad8(TS + 16); }
+__host__ __device__ __forceinline__ int scan_tab_words(int TS) { return (TS + 16) / 2; }
+
+// The candidate a table entry names: u at position p.  A window whose entries are all -inf
+// may carry no position (stored as 0xffff), which reads as -inf.
+__device__ __forceinline__ Cand table_cand(const float *u, int un, int p)
+{
+    const float v = u[min(p, un - 1)];
+    return Cand{p < un ? v : -INFINITY, p};
+}
 
 // Words of a side's LDS (0 for a side without moves); a multiple of 8.
 __host__ __device__ __forceinline__ int side_words(int TS, int w)
@@ -337,9 +341,10 @@ __device__ __forceinline__ void dpp_scan_step(Cand &acc, int &flag)
 
 // One wave's segmented max-scan of u[e] over e in [r0, r1) (both multiples of 8), whose
 // segments are [phi + m w, phi + (m + 1) w) cut to the range (the range starts and ends
-// segments).  FWD: prefix maxima g(e) over [segment start, e], written at tg[pad8(e - glo)]
-// for runs inside [glo, glo + TS + 16); otherwise suffix maxima h(e) over [e, segment end],
-// written at tg[pad8(e)] for runs inside [0, TS).
+// segments).  FWD: the positions of the prefix maxima g(e) over [segment start, e],
+// written at tg[e - glo] for runs inside [glo, glo + TS + 16); otherwise those of the
+// suffix maxima h(e) over [e, segment end], written at tg[e] for runs inside [0, TS); a
+// run's 8 positions go out as one 16-byte store.
 // Lane l of a pass holds the run of 8 entries t = p0 + 8 l .. p0 + 8 l + 7 in scan order
 // (e = r0 + t forward, r1 - 1 - t backward).  A first pass over the run gives the lane's
 // total; DPP row shifts within rows of 16 lanes and row broadcasts of lanes 15 and 31
@@ -347,7 +352,7 @@ __device__ __forceinline__ void dpp_scan_step(Cand &acc, int &flag)
 template <bool FWD>
 __device__ __forceinline__ void window_scan(const float *__restrict__ u, int un, int w, int phi,
                                             int r0, int r1, int glo, int TS,
-                                            float *__restrict__ tg, int lane)
+                                            uint16_t *__restrict__ tg, int lane)
 {
     const Cand none = {-INFINITY, -1};
     const int len = r1 - r0;
@@ -399,12 +404,15 @@ __device__ __forceinline__ void window_scan(const float *__restrict__ u, int un,
         // of 8)
         const int i0 = FWD ? e0 - glo : e0 - 7;
         if (t0 < len && i0 >= 0 && i0 < (FWD ? TS + 16 : TS)) {
-            float2 *out = reinterpret_cast<float2 *>(tg) + pad8(i0);
+            unsigned pos[8];
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 absorb<FWD>(run, x[q], FWD ? e0 + q : e0 - q, (mask >> q) & 1);
-                out[FWD ? q : 7 - q] = make_float2(run.v, __int_as_float(run.e));
+                pos[FWD ? q : 7 - q] = (unsigned)run.e & 0xffffu;
             }
+            *reinterpret_cast<uint4 *>(tg + i0) =
+                make_uint4(pos[0] | pos[1] << 16, pos[2] | pos[3] << 16, pos[4] | pos[5] << 16,
+                           pos[6] | pos[7] << 16);
         }
     }
 }
@@ -421,7 +429,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
     const int S = a.S, w_up = a.w_up, w_down = a.w_down;
     const int jlo = s0 - w_down;                        // Wl[i] holds next state jlo + i
     const int nwl = TS + w_down + w_up;
-    const int wd_words = side_words(TS, w_down), tp2 = pad8(TS + 16);
+    const int wd_words = side_words(TS, w_down), tb = scan_tab_words(TS);
     float *const side_d = smem, *const side_c = smem + wd_words;   // discharge, charge
     float *Wl = smem + wd_words + side_words(TS, w_up);
 
@@ -574,7 +582,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
             if (w == 0) continue;
             const int n = TS + w - 1, un = scan_un(TS, w);
             float *const u = sd ? side_c : side_d;
-            float *tg = u + un + (task & 1) * scan_tab_words(TS);
+            uint16_t *tg = reinterpret_cast<uint16_t *>(u + un + (task & 1) * scan_tab_words(TS));
             // split point: a segment boundary phi + m w near n / 2 that is a multiple of 8
             int phi = 0, split = un;
             if (G == 2 && w >= 8) {
@@ -607,10 +615,10 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
         double best = -INFINITY;
         int bj = s;
         if (w_down) {
-            const float2 *t = reinterpret_cast<const float2 *>(side_d + scan_un(TS, w_down));
-            const float2 h = t[tp2 + pad8(o)], g = t[pad8(o + w_down - 1 - scan_glo(w_down))];
-            const Cand m = better<true>(Cand{h.x, __float_as_int(h.y)},
-                                        Cand{g.x, __float_as_int(g.y)});
+            const int un = scan_un(TS, w_down);
+            const uint16_t *t = reinterpret_cast<const uint16_t *>(side_d + un);
+            const int ph = t[2 * tb + o], pg = t[o + w_down - 1 - scan_glo(w_down)];
+            const Cand m = better<true>(table_cand(side_d, un, ph), table_cand(side_d, un, pg));
             if (m.v > NEG) {
                 best = (double)Wl[m.e] + A_d * (double)(m.e - w_down - o) - cst;
                 bj = jlo + m.e;
@@ -622,10 +630,10 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
             bj = s;
         }
         if (w_up) {
-            const float2 *t = reinterpret_cast<const float2 *>(side_c + scan_un(TS, w_up));
-            const float2 h = t[tp2 + pad8(o)], g = t[pad8(o + w_up - 1 - scan_glo(w_up))];
-            const Cand m = better<true>(Cand{h.x, __float_as_int(h.y)},
-                                        Cand{g.x, __float_as_int(g.y)});
+            const int un = scan_un(TS, w_up);
+            const uint16_t *t = reinterpret_cast<const uint16_t *>(side_c + un);
+            const int ph = t[2 * tb + o], pg = t[o + w_up - 1 - scan_glo(w_up)];
+            const Cand m = better<true>(table_cand(side_c, un, ph), table_cand(side_c, un, pg));
             if (m.v > NEG) {
                 const double v = (double)Wl[w_down + 1 + m.e] + A_c * (double)(m.e + 1 - o) - cst;
                 if (v > best) {

@@ -152,12 +152,12 @@ def test_iid_lds_limit_and_workspace_rules(L):
 
 def test_windows_beyond_lds_are_rejected_before_device_work(L):
     # the smallest tile (64 outputs, one wave) holds, per side, the u array over 63 + w next
-    # states (rounded up to 8) and two window tables of 80 pairs (one spare pair per 8),
-    # the expectation row over 64 + w_up + w_down next states and row k of P_t (K = 3,
-    # padded to 8) in 160 KiB: up to +-10009, not +-10010
-    pb = _pb(S=32767, w_up=10010, w_down=10010)
+    # states (rounded up to 8) and two tables of 80 16-bit positions, the expectation row
+    # over 64 + w_up + w_down next states and row k of P_t (K = 3, padded to 8) in 160 KiB:
+    # up to +-10148, not +-10149
+    pb = _pb(S=32767, w_up=10149, w_down=10149)
     assert L.dp_workspace_bytes(ctypes.byref(pb)) == 0
     assert L.dp_solve(ctypes.byref(pb), 1, 1, None, 1, None, None, 256, 1 << 30, None) == -7
     assert b"LDS" in L.dp_last_error()
-    pb = _pb(S=32767, w_up=10009, w_down=10009)
+    pb = _pb(S=32767, w_up=10148, w_down=10148)
     assert L.dp_workspace_bytes(ctypes.byref(pb)) > 0
