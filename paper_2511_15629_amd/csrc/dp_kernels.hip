@@ -436,6 +436,24 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
     const float NEG = -INFINITY;
     float lam = 0.0f, shift = 0.0f;
     double off_next = 0.0, rsum_m1 = 0.0;
+    // u arrays of both sides, formed as the expectation row is written: discharge
+    // e = 0 .. TS + w_down - 2 at next state s0 - w_down + e (Wl[e]); charge
+    // e = 0 .. TS + w_up - 2 at next state s0 + 1 + e (Wl[w_down + 1 + e]); -inf up to the
+    // arrays' rounded length.  Output o's window is e = o .. o + w - 1 on either side.
+    float Ad = 0.0f, Ac = 0.0f;                         // FP32 slopes (lam known first)
+    const int nd = w_down ? TS + w_down - 1 : 0, nc = w_up ? TS + w_up - 1 : 0;
+    auto put = [&](int i, float v) {                    // next state jlo + i, value v
+        Wl[i] = v;
+        const float jf = (float)(jlo + i);
+        if (i < nd) side_d[i] = fmaf(Ad, jf, v);
+        const int ec = i - w_down - 1;
+        if (ec >= 0 && ec < nc) side_c[ec] = fmaf(Ac, jf, v);
+    };
+    {
+        const int ud = w_down ? scan_un(TS, w_down) : 0, uc = w_up ? scan_un(TS, w_up) : 0;
+        for (int e = nd + tid; e < ud; e += NW * 64) side_d[e] = NEG;
+        for (int e = nc + tid; e < uc; e += NW * 64) side_c[e] = NEG;
+    }
     if (a.Vn) {
         // Fused expectation (the single solve): the block forms the row it needs,
         // W_t[k][j] = sum_k' P_t[k][k'] V_{t+1}[k'][j] over the staged next states, from the
@@ -448,6 +466,8 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
         shift = a.Vn[0];                           // the stage's normalisation V_{t+1}[0][0]
         off_next = a.off_next[0];
         rsum_m1 = a.rho1 ? a.rho1[k] : 0.0;
+        Ad = (float)slope_discharge(lam, a.pay);
+        Ac = (float)slope_charge(lam, a.pay);
         const int K = a.K;
         const float *Pk = a.P + (size_t)k * K;
         // Row k of P_t goes to LDS (zero-padded to a multiple of 8), its loads issued before
@@ -519,7 +539,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const int j = j0 + c, i = j - jlo;
-                if (i >= 0 && i < nwl) Wl[i] = (j >= 0 && j < S) ? av[c] : NEG;
+                if (i >= 0 && i < nwl) put(i, (j >= 0 && j < S) ? av[c] : NEG);
             }
         }
     } else {
@@ -543,31 +563,19 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
                 off_next = a.off_next[0];
                 if (a.rho1) rsum_m1 = a.rho1[k];
                 else if (a.P) rsum_m1 = row_sum_f64(a.P + (size_t)k * a.K, a.K, tid & 63) - 1.0;
+                Ad = (float)slope_discharge(lam, a.pay);
+                Ac = (float)slope_charge(lam, a.pay);
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int i = i4 + u * NW * 64 + tid;
-                if (i < nwl) Wl[i] = w[u];
+                if (i < nwl) put(i, w[u]);
             }
         }
     }
     sweep_sync<NW>();
 
-    // u arrays of both sides: discharge e = 0 .. TS + w_down - 2 at next state
-    // s0 - w_down + e (Wl[e]); charge e = 0 .. TS + w_up - 2 at next state s0 + 1 + e
-    // (Wl[w_down + 1 + e]); -inf up to the arrays' rounded length.  Output o's window is
-    // e = o .. o + w - 1 on either side.
     const double A_d = slope_discharge(lam, a.pay), A_c = slope_charge(lam, a.pay);
-    {
-        const float Ad = (float)A_d, Ac = (float)A_c;
-        const int nd = w_down ? TS + w_down - 1 : 0, nc = w_up ? TS + w_up - 1 : 0;
-        const int ud = w_down ? scan_un(TS, w_down) : 0, uc = w_up ? scan_un(TS, w_up) : 0;
-        for (int e = tid; e < ud; e += NW * 64)
-            side_d[e] = e < nd ? fmaf(Ad, (float)(jlo + e), Wl[e]) : NEG;
-        for (int e = tid; e < uc; e += NW * 64)
-            side_c[e] = e < nc ? fmaf(Ac, (float)(s0 + 1 + e), Wl[w_down + 1 + e]) : NEG;
-    }
-    sweep_sync<NW>();
 
     // Prefix and suffix maxima.  Tasks 0..3 = g_d, h_d, g_c, h_c; with four or more waves
     // each task has NW / 4 waves (two of them split the array at a segment boundary that is
