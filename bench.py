@@ -178,6 +178,10 @@ def roofline_of(inst, timing, traffic=None):
             "traffic_GBps": None if traffic is None else round(traffic / avg_s / 1e9, 1),
             "kernel": "sweep_kernel (expectation fused)", "avg_launch_us": round(avg_s * 1e6, 3),
             "launches": n_sweep,
+            # the work unit is the feasible candidate (one VALU lane-instruction each in a
+            # direct evaluation); the kernel takes window maxima by prefix/suffix scans, so
+            # its time is set by staging the expectation row and by per-stage latency
+            "work": "feasible candidates per launch at 1 VALU lane-op each",
         }
     exp_avg = max(exp_ms / 1e3 / max(n_exp, 1), 1e-12)
     exp_flop = 2.0 * inst.K * inst.K * inst.storage.S
