@@ -302,6 +302,16 @@ __device__ __forceinline__ Cand table_cand(const float *u, int un, int p)
     return Cand{p < un ? v : -INFINITY, p};
 }
 
+// Short move ranges take the direct maximum over the whole range (an add and half a
+// v_max3 per candidate, on chunks of DIRECT_D moves for DIRECT_R outputs per lane); longer
+// ones the window scans of the hoisted payoff, whose cost per output does not grow with the
+// range.
+constexpr int DIRECT_SPAN = 96, DIRECT_R = 4, DIRECT_D = 8;
+__host__ __device__ __forceinline__ bool sweep_direct(int w_up, int w_down)
+{
+    return w_up + w_down + 1 <= DIRECT_SPAN;
+}
+
 // Words of a side's LDS (0 for a side without moves); a multiple of 8.
 __host__ __device__ __forceinline__ int side_words(int TS, int w)
 {
@@ -429,9 +439,16 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
     const int S = a.S, w_up = a.w_up, w_down = a.w_down;
     const int jlo = s0 - w_down;                        // Wl[i] holds next state jlo + i
     const int nwl = TS + w_down + w_up;
-    const int wd_words = side_words(TS, w_down), tb = scan_tab_words(TS);
+    // direct mode: the W row (-inf up to wl_alloc) and the reward row over nchunk chunks;
+    // scan mode: both sides' u arrays and tables, then the W row
+    const bool direct = sweep_direct(w_up, w_down);
+    const int span = w_up + w_down + 1;
+    const int nchunk = (span + DIRECT_D - 1) / DIRECT_D;
+    const int wl_alloc = (TS + span + DIRECT_D + 3) & ~3;
+    const int wd_words = direct ? 0 : side_words(TS, w_down), tb = scan_tab_words(TS);
     float *const side_d = smem, *const side_c = smem + wd_words;   // discharge, charge
-    float *Wl = smem + wd_words + side_words(TS, w_up);
+    float *Wl = smem + wd_words + (direct ? 0 : side_words(TS, w_up));
+    float *rl = Wl + wl_alloc;                          // direct mode: reward row
 
     const float NEG = -INFINITY;
     float lam = 0.0f, shift = 0.0f;
@@ -441,7 +458,8 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
     // e = 0 .. TS + w_up - 2 at next state s0 + 1 + e (Wl[w_down + 1 + e]); -inf up to the
     // arrays' rounded length.  Output o's window is e = o .. o + w - 1 on either side.
     float Ad = 0.0f, Ac = 0.0f;                         // FP32 slopes (lam known first)
-    const int nd = w_down ? TS + w_down - 1 : 0, nc = w_up ? TS + w_up - 1 : 0;
+    const int nd = (w_down && !direct) ? TS + w_down - 1 : 0;
+    const int nc = (w_up && !direct) ? TS + w_up - 1 : 0;
     auto put = [&](int i, float v) {                    // next state jlo + i, value v
         Wl[i] = v;
         const float jf = (float)(jlo + i);
@@ -449,7 +467,9 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
         const int ec = i - w_down - 1;
         if (ec >= 0 && ec < nc) side_c[ec] = fmaf(Ac, jf, v);
     };
-    {
+    if (direct) {
+        for (int i = nwl + tid; i < wl_alloc; i += NW * 64) Wl[i] = NEG;
+    } else {
         const int ud = w_down ? scan_un(TS, w_down) : 0, uc = w_up ? scan_un(TS, w_up) : 0;
         for (int e = nd + tid; e < ud; e += NW * 64) side_d[e] = NEG;
         for (int e = nc + tid; e < uc; e += NW * 64) side_c[e] = NEG;
@@ -477,7 +497,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
         // state 0 and are replaced by -inf.
         constexpr int RB = 8;
         const int K8 = (K + RB - 1) & ~(RB - 1);
-        float *prow = Wl + ((nwl + 3) & ~3);       // [K8]
+        float *prow = direct ? rl + nchunk * DIRECT_D : Wl + ((nwl + 3) & ~3);   // [K8]
         const int q0 = jlo >> 2;                   // quads of next states (floor: jlo < 0 ok)
         const int q1 = (jlo + nwl + 3) >> 2;
         float pmine[4];                            // this thread's first P entries
@@ -573,9 +593,95 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
             }
         }
     }
+    if (direct) {
+        for (int i = tid; i < nchunk * DIRECT_D; i += NW * 64)
+            rl[i] = i < span ? move_reward(lam, i - w_down, a.pay) : NEG;
+    }
     sweep_sync<NW>();
 
     const double A_d = slope_discharge(lam, a.pay), A_c = slope_charge(lam, a.pay);
+    const double Ct = off_next + (double)shift;   // shift = V_{t+1}[0][0], the normalisation
+    // W_t was formed from the normalised V_{t+1}; its true value adds rho_k C_{t+1}, of which
+    // C_{t+1} is carried by the offset and (rho_k - 1) C_{t+1} goes into the row (exactly 0
+    // when the row sums to 1)
+    const double corr = rsum_m1 * off_next - (double)shift;
+    const double cst = (double)a.pay.c_start;
+    auto emit = [&](int o, double best, int bj) {      // output s0 + o < S
+        const int s = s0 + o;
+        const float vn = (float)(best + corr);
+        const size_t idx = (size_t)k * S + s;
+        a.vnorm[(size_t)k * a.ldv + s] = vn;
+        // outputs the next launch does not read go out as non-temporal stores
+        if (a.vabs) __builtin_nontemporal_store((float)((double)vn + Ct), &a.vabs[idx]);
+        if (a.pol) __builtin_nontemporal_store((int16_t)bj, &a.pol[idx]);
+        if (a.ckpt_v) __builtin_nontemporal_store(vn, &a.ckpt_v[idx]);
+    };
+    if (direct) {
+        // Direct maximum over the move range: per output the running maximum of
+        // W[j] + r(j - s) in FP32 over chunks of D moves and the first chunk that raised
+        // it; that chunk is rescanned for its first move whose candidate (the same
+        // operands, so the same bits) equals the maximum: the smallest next state.  The
+        // chosen candidate is re-evaluated in FP64 as in the scan path.
+        constexpr int R = DIRECT_R, D = DIRECT_D;
+        for (int g = tid; g < TS / R; g += NW * 64) {
+            const int o0 = g * R;
+            float best[R];
+            int cid[R];
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                best[i] = NEG;
+                cid[i] = 0;
+            }
+            for (int c = 0; c < nchunk; ++c) {
+                float w[R + D], r[D];
+                const float4 *ws4 = reinterpret_cast<const float4 *>(Wl + o0 + c * D);
+                const float4 *rs4 = reinterpret_cast<const float4 *>(rl + c * D);
+#pragma unroll
+                for (int m = 0; m < (R + D) / 4; ++m) {
+                    const float4 v = ws4[m];
+                    w[4 * m] = v.x;
+                    w[4 * m + 1] = v.y;
+                    w[4 * m + 2] = v.z;
+                    w[4 * m + 3] = v.w;
+                }
+#pragma unroll
+                for (int m = 0; m < D / 4; ++m) {
+                    const float4 v = rs4[m];
+                    r[4 * m] = v.x;
+                    r[4 * m + 1] = v.y;
+                    r[4 * m + 2] = v.z;
+                    r[4 * m + 3] = v.w;
+                }
+#pragma unroll
+                for (int i = 0; i < R; ++i) {
+                    float m = best[i];
+#pragma unroll
+                    for (int d = 0; d < D; ++d) m = fmaxf(m, w[i + d] + r[d]);
+                    cid[i] = m > best[i] ? c : cid[i];
+                    best[i] = m;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                const int o = o0 + i;
+                if (s0 + o >= S) break;
+                const int b = o + cid[i] * D;            // Wl index of the chunk's first move
+                int arg = 0;
+#pragma unroll
+                for (int d = D - 1; d >= 0; --d)
+                    arg = Wl[b + d] + rl[cid[i] * D + d] == best[i] ? d : arg;
+                const int e = b + arg, dm = e - w_down - o;       // the move j - s
+                const double v = dm == 0 ? (double)Wl[e]
+                                         : (double)Wl[e] + (dm > 0 ? A_c : A_d) * (double)dm - cst;
+                emit(o, v, jlo + e);
+            }
+        }
+        if (k == 0 && tile == 0 && tid == 0) {
+            a.off_cur[0] = Ct;
+            if (a.ckpt_off) a.ckpt_off[0] = Ct;
+        }
+        return;
+    }
 
     // Prefix and suffix maxima.  Tasks 0..3 = g_d, h_d, g_c, h_c; with four or more waves
     // each task has NW / 4 waves (two of them split the array at a segment boundary that is
@@ -609,12 +715,6 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
     }
     sweep_sync<NW>();
 
-    const double Ct = off_next + (double)shift;   // shift = V_{t+1}[0][0], the normalisation
-    // W_t was formed from the normalised V_{t+1}; its true value adds rho_k C_{t+1}, of which
-    // C_{t+1} is carried by the offset and (rho_k - 1) C_{t+1} goes into the row (exactly 0
-    // when the row sums to 1)
-    const double corr = rsum_m1 * off_next - (double)shift;
-    const double cst = (double)a.pay.c_start;
     for (int o = tid; o < TS; o += NW * 64) {
         const int s = s0 + o;
         if (s >= S) break;
@@ -650,13 +750,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
                 }
             }
         }
-        const float vn = (float)(best + corr);
-        const size_t idx = (size_t)k * S + s;
-        a.vnorm[(size_t)k * a.ldv + s] = vn;
-        // outputs the next launch does not read go out as non-temporal stores
-        if (a.vabs) __builtin_nontemporal_store((float)((double)vn + Ct), &a.vabs[idx]);
-        if (a.pol) __builtin_nontemporal_store((int16_t)bj, &a.pol[idx]);
-        if (a.ckpt_v) __builtin_nontemporal_store(vn, &a.ckpt_v[idx]);
+        emit(o, best, bj);
     }
     if (k == 0 && tile == 0 && tid == 0) {
         a.off_cur[0] = Ct;
@@ -676,6 +770,13 @@ int sweep_tile(const SweepShape &sh) { return sh.TS; }
 
 size_t sweep_lds_bytes(const SweepShape &sh, int w_up, int w_down, int K)
 {
+    if (sweep_direct(w_up, w_down)) {
+        // the W row with its -inf slack, the reward row, and row k of P_t when fused
+        const int span = w_up + w_down + 1;
+        const size_t wl = ((size_t)sh.TS + span + DIRECT_D + 3) & ~(size_t)3;
+        const size_t rl = (size_t)((span + DIRECT_D - 1) / DIRECT_D) * DIRECT_D;
+        return sizeof(float) * (wl + rl + (size_t)((K + 7) & ~7));
+    }
     // both sides' u arrays and window tables, the expectation row over the tile's windows
     // (a multiple of 4 entries), and with the fused expectation (K > 0) row k of P_t padded
     // to a multiple of 8

@@ -56,6 +56,10 @@ RAGGED = [
     dict(seed=9, T=7, K=2, S=129, wu=1, wd=100),
     dict(seed=10, T=1, K=6, S=300, wu=20, wd=35, c_start=1.0),    # a single stage
     dict(seed=11, T=1, K=1, S=2, wu=1, wd=1),                     # the smallest problem
+    # the direct maximum takes move ranges of up to 96 moves (idle included), the window
+    # scans longer ones: the two sides of that boundary
+    dict(seed=12, T=4, K=9, S=900, wu=50, wd=45, c_start=1.5),
+    dict(seed=13, T=4, K=9, S=900, wu=50, wd=46, c_start=1.5),
 ]
 
 
@@ -187,9 +191,11 @@ def test_repeat_runs_are_bitwise_identical(dp):
                                    (64, 1)])
 def test_tile_shapes_give_bitwise_identical_results(dp, shape):
     # the second instance has windows of 153 and 174 moves on 1966 levels: every tile then
-    # holds windows wholly outside [0, S) at the edges, whose scans carry no position
+    # holds windows wholly outside [0, S) at the edges, whose scans carry no position; the
+    # third one's 51 moves take the direct maximum
     for inst in (wl.random_small(31, 6, 21, 1100, 260, 180, c_start=3.0, lam_lo=-60.0),
-                 wl.random_small(32, 4, 10, 1966, 153, 174, c_start=1.0)):
+                 wl.random_small(32, 4, 10, 1966, 153, 174, c_start=1.0),
+                 wl.random_small(33, 5, 7, 700, 30, 20, c_start=2.0)):
         dp.set_sweep_shape()
         ref = gpu_solve(dp, inst, store_all=True)
         try:
