@@ -431,7 +431,8 @@ __device__ __forceinline__ void window_scan(const float *__restrict__ u, int un,
 // LDS: per side (discharge, then charge) the u array and the g and h tables; the
 // expectation row over next states s0 - w_down .. s0 + TS - 1 + w_up; with the fused
 // expectation, row k of P_t.
-template <int NW>
+// DIRECT: the block's move range takes the direct maximum (sweep_direct(w_up, w_down)).
+template <int NW, bool DIRECT>
 __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, const int tile,
                                             const int TS, float *smem, const int tid)
 {
@@ -441,7 +442,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
     const int nwl = TS + w_down + w_up;
     // direct mode: the W row (-inf up to wl_alloc) and the reward row over nchunk chunks;
     // scan mode: both sides' u arrays and tables, then the W row
-    const bool direct = sweep_direct(w_up, w_down);
+    constexpr bool direct = DIRECT;
     const int span = w_up + w_down + 1;
     const int nchunk = (span + DIRECT_D - 1) / DIRECT_D;
     const int wl_alloc = (TS + span + DIRECT_D + 3) & ~3;
@@ -467,7 +468,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
         const int ec = i - w_down - 1;
         if (ec >= 0 && ec < nc) side_c[ec] = fmaf(Ac, jf, v);
     };
-    if (direct) {
+    if constexpr (direct) {
         for (int i = nwl + tid; i < wl_alloc; i += NW * 64) Wl[i] = NEG;
     } else {
         const int ud = w_down ? scan_un(TS, w_down) : 0, uc = w_up ? scan_un(TS, w_up) : 0;
@@ -593,7 +594,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
             }
         }
     }
-    if (direct) {
+    if constexpr (direct) {
         for (int i = tid; i < nchunk * DIRECT_D; i += NW * 64)
             rl[i] = i < span ? move_reward(lam, i - w_down, a.pay) : NEG;
     }
@@ -616,7 +617,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
         if (a.pol) __builtin_nontemporal_store((int16_t)bj, &a.pol[idx]);
         if (a.ckpt_v) __builtin_nontemporal_store(vn, &a.ckpt_v[idx]);
     };
-    if (direct) {
+    if constexpr (direct) {
         // Direct maximum over the move range: per output the running maximum of
         // W[j] + r(j - s) in FP32 over chunks of D moves and the first chunk that raised
         // it; that chunk is rescanned for its first move whose candidate (the same
@@ -758,12 +759,12 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
     }
 }
 
-template <int NW>
+template <int NW, bool DIRECT>
 __global__ __launch_bounds__(NW * 64) void sweep_kernel(SweepArgs a, int TS)
 {
     extern __shared__ float4 smem4[];
-    sweep_block<NW>(a, blockIdx.y, blockIdx.x, TS, reinterpret_cast<float *>(smem4),
-                    threadIdx.x);
+    sweep_block<NW, DIRECT>(a, blockIdx.y, blockIdx.x, TS, reinterpret_cast<float *>(smem4),
+                            threadIdx.x);
 }
 
 int sweep_tile(const SweepShape &sh) { return sh.TS; }
@@ -802,10 +803,16 @@ hipError_t launch_sweep(const SweepArgs &a, const SweepShape &sh, hipStream_t st
 {
     dim3 grid((a.S + sh.TS - 1) / sh.TS, a.K);
     const size_t lds = sweep_lds_bytes(sh, a.w_up, a.w_down, a.Vn ? a.K : 0);
-#define X(nw)                                                                               \
-    if (sh.NW == nw) {                                                                      \
-        hipLaunchKernelGGL((sweep_kernel<nw>), grid, dim3(nw * 64), lds, stream, a, sh.TS); \
-        return hipGetLastError();                                                           \
+    const bool direct = sweep_direct(a.w_up, a.w_down);
+#define X(nw)                                                                                 \
+    if (sh.NW == nw) {                                                                        \
+        if (direct)                                                                           \
+            hipLaunchKernelGGL((sweep_kernel<nw, true>), grid, dim3(nw * 64), lds, stream, a,  \
+                               sh.TS);                                                        \
+        else                                                                                  \
+            hipLaunchKernelGGL((sweep_kernel<nw, false>), grid, dim3(nw * 64), lds, stream, a, \
+                               sh.TS);                                                        \
+        return hipGetLastError();                                                             \
     }
     DP_SWEEP_WAVES(X)
 #undef X
@@ -1185,9 +1192,12 @@ __global__ __launch_bounds__(NW * 64 * tiles_per_block<NW>()) void batched_sweep
     a.pol = d.pol ? d.pol + (size_t)(t - 1) * d.K * d.S : nullptr;
     a.ckpt_v = nullptr;
     a.ckpt_off = nullptr;
-    sweep_block<NW>(a, it.k, it.tile, TS,
-                    reinterpret_cast<float *>(smem4) + (size_t)slot * lds_tile,
-                    TPB > 1 ? (int)(threadIdx.x & 63) : (int)threadIdx.x);
+    float *smem = reinterpret_cast<float *>(smem4) + (size_t)slot * lds_tile;
+    const int tid = TPB > 1 ? (int)(threadIdx.x & 63) : (int)threadIdx.x;
+    if (sweep_direct(a.w_up, a.w_down))     // per instance: a class can hold both kinds
+        sweep_block<NW, true>(a, it.k, it.tile, TS, smem, tid);
+    else
+        sweep_block<NW, false>(a, it.k, it.tile, TS, smem, tid);
 }
 
 __global__ __launch_bounds__(256) void batched_contract_kernel(const BatchDesc *__restrict__ desc,
