@@ -695,15 +695,20 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
             const int sd = task >> 1;
             const int w = sd ? w_up : w_down;
             if (w == 0) continue;
-            const int n = TS + w - 1, un = scan_un(TS, w);
+            const int un = scan_un(TS, w);
             float *const u = sd ? side_c : side_d;
             uint16_t *tg = reinterpret_cast<uint16_t *>(u + un + (task & 1) * scan_tab_words(TS));
-            // split point: a segment boundary phi + m w near n / 2 that is a multiple of 8
+            // split point: the multiple of 8 nearest un / 2, made a segment boundary by the
+            // shift phi = split mod w (any shift in [0, w) gives segments of w, and the window
+            // maxima do not depend on it), so that neither wave runs a pass more than the
+            // other for a few entries
             int phi = 0, split = un;
-            if (G == 2 && w >= 8) {
-                const int m = max(1, (n + w) / (2 * w));
-                phi = (8 - (m * w) % 8) % 8;
-                if (phi + m * w < un) split = phi + m * w;
+            if (G == 2) {
+                const int half = ((un >> 1) + 4) & ~7;
+                if (half > 0 && half < un) {
+                    split = half;
+                    phi = half % w;
+                }
             }
             const int gw = NW >= 8 ? wave % 2 : 0;
             if (gw == 1 && split == un) continue;
