@@ -387,10 +387,15 @@ __device__ __forceinline__ void window_scan(const float *__restrict__ u, int un,
             const int dm = FWD ? e0 - phi : phi - 1 - e0;      // entry q: dm + q = 0 mod w
             int r = dm % w;
             r = r < 0 ? r + w : r;
+            if (w >= 8) {                              // at most one boundary in the run
+                const int q1 = r == 0 ? 0 : w - r;
+                mask |= q1 < 8 ? 1 << q1 : 0;
+            } else {
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                mask |= (r == 0) << q;
-                r = r + 1 == w ? 0 : r + 1;
+                for (int q = 0; q < 8; ++q) {
+                    mask |= (r == 0) << q;
+                    r = r + 1 == w ? 0 : r + 1;
+                }
             }
         }
         Cand acc = lane == 0 ? carry : none;
