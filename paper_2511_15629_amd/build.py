@@ -16,6 +16,11 @@ HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed FP32 (v_pk_*_f32) in any kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # the first ten kernel arguments (up to 16 SGPRs) preloaded at dispatch: the single
+    # solve's sweep launch, one per stage, then addresses its first loads without a load of
+    # its argument block (3% of the year-long solve); the compiler keeps a prologue that
+    # loads the same registers where the firmware does not preload
+    "-mllvm", "-amdgpu-kernarg-preload-count=10",
     "-Wno-unused-command-line-argument",
 ]
 

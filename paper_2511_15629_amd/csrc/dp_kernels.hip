@@ -769,9 +769,25 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
     }
 }
 
+// The fields that address a block's first loads (row k of P_t, the first rows of V_{t+1})
+// come first as scalar arguments: the library is built to have the first kernel arguments
+// preloaded into SGPRs at dispatch, so these loads issue without waiting for a load of the
+// argument block (the struct itself is not preloaded).  They override the struct's copies.
 template <int NW, bool DIRECT>
-__global__ __launch_bounds__(NW * 64) void sweep_kernel(SweepArgs a, int TS)
+__global__ __launch_bounds__(NW * 64) void sweep_kernel(const float *Vn, const float *lam,
+                                                        const float *P, const double *rho1,
+                                                        int TS, int ldvn, int K, int S,
+                                                        int w_up, int w_down, SweepArgs a)
 {
+    a.Vn = Vn;
+    a.lam = lam;
+    a.P = P;
+    a.rho1 = rho1;
+    a.ldvn = ldvn;
+    a.K = K;
+    a.S = S;
+    a.w_up = w_up;
+    a.w_down = w_down;
     extern __shared__ float4 smem4[];
     sweep_block<NW, DIRECT>(a, blockIdx.y, blockIdx.x, TS, reinterpret_cast<float *>(smem4),
                             threadIdx.x);
@@ -817,11 +833,13 @@ hipError_t launch_sweep(const SweepArgs &a, const SweepShape &sh, hipStream_t st
 #define X(nw)                                                                                 \
     if (sh.NW == nw) {                                                                        \
         if (direct)                                                                           \
-            hipLaunchKernelGGL((sweep_kernel<nw, true>), grid, dim3(nw * 64), lds, stream, a,  \
-                               sh.TS);                                                        \
+            hipLaunchKernelGGL((sweep_kernel<nw, true>), grid, dim3(nw * 64), lds, stream,     \
+                               a.Vn, a.lam, a.P, a.rho1, sh.TS, a.ldvn, a.K, a.S, a.w_up,     \
+                               a.w_down, a);                                                  \
         else                                                                                  \
-            hipLaunchKernelGGL((sweep_kernel<nw, false>), grid, dim3(nw * 64), lds, stream, a, \
-                               sh.TS);                                                        \
+            hipLaunchKernelGGL((sweep_kernel<nw, false>), grid, dim3(nw * 64), lds, stream,    \
+                               a.Vn, a.lam, a.P, a.rho1, sh.TS, a.ldvn, a.K, a.S, a.w_up,     \
+                               a.w_down, a);                                                  \
         return hipGetLastError();                                                             \
     }
     DP_SWEEP_WAVES(X)
