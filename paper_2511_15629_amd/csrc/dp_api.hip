@@ -140,8 +140,12 @@ SolveLayout solve_layout(const dp_problem *pb)
     L.vB = o; o += plane;
     L.off = o; o += align256(sizeof(double) * ((size_t)pb->T + 2));
     L.flag = o; o += 256;
-    // rho_k - 1 of P_t, up to 32 stages per row-sum launch
-    L.npk = pb->T < 32 ? pb->T : 32;
+    // rho_k - 1 of P_t for every stage, formed by one launch before the first stage (a launch
+    // between two stages adds its duration and a launch gap to the chain); for very long
+    // horizons the ring is halved until it takes at most 64 MiB
+    L.npk = pb->T;
+    while (L.npk > 32 && sizeof(double) * (size_t)L.npk * pb->K > ((size_t)64 << 20))
+        L.npk = (L.npk + 1) / 2;
     L.rho = o; o += align256(sizeof(double) * (size_t)L.npk * pb->K);
     L.total = o;
     return L;
