@@ -1649,7 +1649,7 @@ hipError_t launch_adjoint_scale(const float *seed, size_t n, double *scale, hipS
 // ------------------------------------------------------------------------------------
 // grad_P_t = nu_t V_{t+1}^T for a group of consecutive stages (one launch per group; the
 // transport mu_{t+1} = P_t^T nu_t is the expectation kernel with A = P^T, per stage).
-// Block (x, y) = one 16 x 16 tile of stage y of the group, 16 waves: wave w reduces the
+// A block = one 16 x 16 tile of one stage of the group, 16 waves: wave w reduces the
 // w-th sixteenth of j (one chunk of prefetched MFMA steps), and the 16 partial tiles are
 // added in wave order, so each gradient entry has one fixed summation order.
 // ------------------------------------------------------------------------------------
@@ -1657,16 +1657,22 @@ constexpr int GRADP_WAVES = 16;
 
 __global__ __launch_bounds__(64 * GRADP_WAVES) void gradP_kernel(
     const float *__restrict__ nu0, size_t nu_stride, int ldn, const float *__restrict__ V0,
-    size_t v_stride, int K, int S, float *__restrict__ gP0)
+    size_t v_stride, int K, int S, int G, float *__restrict__ gP0)
 {
     constexpr int CH = 16;
     __shared__ float part[GRADP_WAVES][256];
-    const float *nu = nu0 + blockIdx.y * nu_stride;
-    const float *V = V0 + blockIdx.y * v_stride;
-    float *gP = gP0 + (size_t)blockIdx.y * K * K;
+    // Blocks are dealt to the 8 XCDs in turn by index: block 8 i + x runs on XCD x.  Stage g
+    // of the group takes XCD g mod 8, so all its tiles read its rows of nu and V through one
+    // L2 (a stage spread over every XCD had each L2 fetch them: 7x the algorithmic bytes).
+    const int ntm = (K + 15) >> 4, nt2 = ntm * ntm;
+    const int xcd = blockIdx.x & 7, bi = blockIdx.x >> 3;
+    const int g = xcd + 8 * (bi / nt2), tile = bi % nt2;
+    if (g >= G) return;                        // the whole block: past the group's stages
+    const float *nu = nu0 + g * nu_stride;
+    const float *V = V0 + g * v_stride;
+    float *gP = gP0 + (size_t)g * K * K;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int ntm = (K + 15) >> 4;
-    const int tm = blockIdx.x % ntm, tn = blockIdx.x / ntm;
+    const int tm = tile % ntm, tn = tile / ntm;
     const int kq = lane >> 4;
     const int arow = tm * 16 + (lane & 15);   // k
     const int bcol = tn * 16 + (lane & 15);   // k'
@@ -1705,8 +1711,9 @@ hipError_t launch_gradP(const float *nu, size_t nu_stride, int ldn, const float 
                         size_t v_stride, int K, int S, int G, float *gP, hipStream_t stream)
 {
     const int nt = (K + 15) / 16;
-    hipLaunchKernelGGL(gradP_kernel, dim3(nt * nt, G), dim3(64 * GRADP_WAVES), 0, stream, nu,
-                       nu_stride, ldn, V, v_stride, K, S, gP);
+    // one block per (stage, tile), stages grouped by XCD (8 blocks per tile slot)
+    hipLaunchKernelGGL(gradP_kernel, dim3(8 * nt * nt * ((G + 7) / 8)), dim3(64 * GRADP_WAVES),
+                       0, stream, nu, nu_stride, ldn, V, v_stride, K, S, G, gP);
     return hipGetLastError();
 }
 
