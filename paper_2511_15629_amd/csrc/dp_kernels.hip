@@ -437,7 +437,8 @@ __device__ __forceinline__ void window_scan(const float *__restrict__ u, int un,
 // expectation row over next states s0 - w_down .. s0 + TS - 1 + w_up; with the fused
 // expectation, row k of P_t.
 // DIRECT: the block's move range takes the direct maximum (sweep_direct(w_up, w_down)).
-template <int NW, bool DIRECT>
+// RB: rows of V_{t+1} per load batch of the fused expectation (fused_rows(K)).
+template <int NW, bool DIRECT, int RB = 8>
 __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, const int tile,
                                             const int TS, float *smem, const int tid)
 {
@@ -484,10 +485,10 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
         // Fused expectation (the single solve): the block forms the row it needs,
         // W_t[k][j] = sum_k' P_t[k][k'] V_{t+1}[k'][j] over the staged next states, from the
         // normalised V_{t+1} and row k of P_t.  Each entry is an FP32 fma chain over k'
-        // ascending from 0, padded with zero terms to a multiple of 4: bitwise the MFMA tile
-        // chain of the expectation kernels.  A thread owns quads of four next states (one
-        // 16-byte load per row), with the next eight rows' loads in flight while eight are
-        // accumulated.
+        // ascending from 0 (zero terms past K add exact zeros): bitwise the MFMA tile chain of
+        // the expectation kernels, which pads to a multiple of 4.  A thread owns quads of four
+        // next states (one 16-byte load per row), with the next RB rows' loads in flight while
+        // RB are accumulated.
         lam = a.lam[k];
         shift = a.Vn[0];                           // the stage's normalisation V_{t+1}[0][0]
         off_next = a.off_next[0];
@@ -496,13 +497,14 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
         Ac = (float)slope_charge(lam, a.pay);
         const int K = a.K;
         const float *Pk = a.P + (size_t)k * K;
-        // Row k of P_t goes to LDS (zero-padded to a multiple of 8), its loads issued before
+        // Row k of P_t goes to LDS (zero-padded to a multiple of RB), its loads issued before
         // the first rows of V_{t+1}, and is read back as broadcasts.  Rows past K enter with
         // P = 0 and the last row's values, adding exact zeros (the chain's sums are never
         // -0), as the tile chain's padding does; quads outside [0, S) read row data at
-        // state 0 and are replaced by -inf.
-        constexpr int RB = 8;
-        const int K8 = (K + RB - 1) & ~(RB - 1);
+        // state 0 and are replaced by -inf.  RB (8 or 10, whichever pads K less) sets how
+        // many of those repeated loads there are: none for K = 20, 50, 100 with 10.
+        static_assert(RB % 2 == 0, "P is read back in pairs");
+        const int K8 = (K + RB - 1) / RB * RB;
         float *prow = direct ? rl + nchunk * DIRECT_D : Wl + ((nwl + 3) & ~3);   // [K8]
         const int q0 = jlo >> 2;                   // quads of next states (floor: jlo < 0 ok)
         const int q1 = (jlo + nwl + 3) >> 2;
@@ -539,14 +541,14 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
             if (q != q0 + tid) load(va, vq, 0);
             float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             auto accumulate = [&](const float4 (&v)[RB], int r0) {
-                const float4 *p4 = reinterpret_cast<const float4 *>(prow + r0);
+                const float2 *p2 = reinterpret_cast<const float2 *>(prow + r0);
 #pragma unroll
-                for (int r4 = 0; r4 < RB / 4; ++r4) {
-                    const float4 pp = p4[r4];
-                    const float pr[4] = {pp.x, pp.y, pp.z, pp.w};
+                for (int r2 = 0; r2 < RB / 2; ++r2) {
+                    const float2 pp = p2[r2];
+                    const float pr[2] = {pp.x, pp.y};
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const float4 x = v[4 * r4 + r];
+                    for (int r = 0; r < 2; ++r) {
+                        const float4 x = v[2 * r2 + r];
                         acc.x = fmaf(pr[r], x.x, acc.x);
                         acc.y = fmaf(pr[r], x.y, acc.y);
                         acc.z = fmaf(pr[r], x.z, acc.z);
@@ -773,7 +775,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs &a, const int k, con
 // come first as scalar arguments: the library is built to have the first kernel arguments
 // preloaded into SGPRs at dispatch, so these loads issue without waiting for a load of the
 // argument block (the struct itself is not preloaded).  They override the struct's copies.
-template <int NW, bool DIRECT>
+template <int NW, bool DIRECT, int RB>
 __global__ __launch_bounds__(NW * 64) void sweep_kernel(const float *Vn, const float *lam,
                                                         const float *P, const double *rho1,
                                                         int TS, int ldvn, int K, int S,
@@ -789,11 +791,21 @@ __global__ __launch_bounds__(NW * 64) void sweep_kernel(const float *Vn, const f
     a.w_up = w_up;
     a.w_down = w_down;
     extern __shared__ float4 smem4[];
-    sweep_block<NW, DIRECT>(a, blockIdx.y, blockIdx.x, TS, reinterpret_cast<float *>(smem4),
+    sweep_block<NW, DIRECT, RB>(a, blockIdx.y, blockIdx.x, TS, reinterpret_cast<float *>(smem4),
                             threadIdx.x);
 }
 
 int sweep_tile(const SweepShape &sh) { return sh.TS; }
+
+// Load batch of the fused expectation: 10 rows when that pads K less than 8 does.
+static int fused_rows(int K) { return (K + 9) / 10 * 10 - K < (K + 7) / 8 * 8 - K ? 10 : 8; }
+// LDS words for row k of P_t padded to its batch (none without the fused expectation)
+static size_t fused_prow_words(int K)
+{
+    if (K <= 0) return 0;
+    const int rb = fused_rows(K);
+    return (size_t)(((K + rb - 1) / rb * rb + 3) & ~3);
+}
 
 size_t sweep_lds_bytes(const SweepShape &sh, int w_up, int w_down, int K)
 {
@@ -802,14 +814,14 @@ size_t sweep_lds_bytes(const SweepShape &sh, int w_up, int w_down, int K)
         const int span = w_up + w_down + 1;
         const size_t wl = ((size_t)sh.TS + span + DIRECT_D + 3) & ~(size_t)3;
         const size_t rl = (size_t)((span + DIRECT_D - 1) / DIRECT_D) * DIRECT_D;
-        return sizeof(float) * (wl + rl + (size_t)((K + 7) & ~7));
+        return sizeof(float) * (wl + rl + fused_prow_words(K));
     }
     // both sides' u arrays and window tables, the expectation row over the tile's windows
     // (a multiple of 4 entries), and with the fused expectation (K > 0) row k of P_t padded
-    // to a multiple of 8
+    // to a multiple of its load batch
     const size_t nwl = ((size_t)sh.TS + w_up + w_down + 3) & ~(size_t)3;
     return sizeof(float) * ((size_t)side_words(sh.TS, w_down) + side_words(sh.TS, w_up) + nwl +
-                            (size_t)((K + 7) & ~7));
+                            fused_prow_words(K));
 }
 
 // waves per block with a kernel, and the tile sizes (outputs per block) allowed
@@ -830,20 +842,24 @@ hipError_t launch_sweep(const SweepArgs &a, const SweepShape &sh, hipStream_t st
     dim3 grid((a.S + sh.TS - 1) / sh.TS, a.K);
     const size_t lds = sweep_lds_bytes(sh, a.w_up, a.w_down, a.Vn ? a.K : 0);
     const bool direct = sweep_direct(a.w_up, a.w_down);
+    const bool rb10 = fused_rows(a.K) == 10;
+#define DP_SWEEP_LAUNCH(nw, dr, rb)                                                           \
+    hipLaunchKernelGGL((sweep_kernel<nw, dr, rb>), grid, dim3(nw * 64), lds, stream, a.Vn,     \
+                       a.lam, a.P, a.rho1, sh.TS, a.ldvn, a.K, a.S, a.w_up, a.w_down, a)
 #define X(nw)                                                                                 \
     if (sh.NW == nw) {                                                                        \
-        if (direct)                                                                           \
-            hipLaunchKernelGGL((sweep_kernel<nw, true>), grid, dim3(nw * 64), lds, stream,     \
-                               a.Vn, a.lam, a.P, a.rho1, sh.TS, a.ldvn, a.K, a.S, a.w_up,     \
-                               a.w_down, a);                                                  \
-        else                                                                                  \
-            hipLaunchKernelGGL((sweep_kernel<nw, false>), grid, dim3(nw * 64), lds, stream,    \
-                               a.Vn, a.lam, a.P, a.rho1, sh.TS, a.ldvn, a.K, a.S, a.w_up,     \
-                               a.w_down, a);                                                  \
+        if (direct) {                                                                         \
+            if (rb10) DP_SWEEP_LAUNCH(nw, true, 10);                                          \
+            else DP_SWEEP_LAUNCH(nw, true, 8);                                                \
+        } else {                                                                              \
+            if (rb10) DP_SWEEP_LAUNCH(nw, false, 10);                                         \
+            else DP_SWEEP_LAUNCH(nw, false, 8);                                               \
+        }                                                                                     \
         return hipGetLastError();                                                             \
     }
     DP_SWEEP_WAVES(X)
 #undef X
+#undef DP_SWEEP_LAUNCH
     return hipErrorInvalidValue;
 }
 
